@@ -1,0 +1,161 @@
+/*
+ * CPU oracle for the data-driven BFS/SSSP hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the package smoke check and the bench's
+ * CPU-baseline leg do.  It shares no code with the HIP library.
+ *
+ * What it computes is the plain definition of the result that the paper's
+ * worklist BFS (Section 4.1, level-by-level BFS listing: a vertex found
+ * while expanding the level-k frontier gets level k+1, starting from the
+ * initial worklist [src]) converges to:
+ *
+ *   level[v] = least number of out-edges on a directed path src -> v,
+ *              0xFFFFFFFF when no path exists;
+ *   dist[v]  = least sum of uint32 weights (each >= 1) over directed paths
+ *              src -> v, 0xFFFFFFFF when no path exists (textbook
+ *              single-source shortest paths; the paper states only BFS).
+ *
+ * Algorithms: a FIFO-queue breadth-first search and a binary-heap Dijkstra
+ * with lazy deletion and a 64-bit distance accumulator.  Both are serial and
+ * deliberately plain.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_INF 0xFFFFFFFFu
+
+/* Serial FIFO breadth-first search over CSR out-edges.
+ * level/parent: caller-owned host arrays of length n.
+ * parent[src] = src, parent[v] = -1 when unreached, otherwise the vertex
+ * that first discovered v.  Returns the number of reached vertices, or -1 on
+ * invalid arguments / allocation failure. */
+int64_t oracle_bfs(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t src,
+                   uint32_t *level, int32_t *parent) {
+    if (n <= 0 || src < 0 || src >= n || !row_ptr || !col || !level) return -1;
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!queue) return -1;
+    for (int32_t v = 0; v < n; ++v) {
+        level[v] = ORACLE_INF;
+        if (parent) parent[v] = -1;
+    }
+    int64_t head = 0, tail = 0;
+    level[src] = 0;
+    if (parent) parent[src] = src;
+    queue[tail++] = src;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (level[v] == ORACLE_INF) {
+                level[v] = level[u] + 1;
+                if (parent) parent[v] = u;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
+    return tail;
+}
+
+/* ---- binary min-heap of (distance, vertex) ---------------------------- */
+typedef struct {
+    uint64_t d;
+    int32_t v;
+} heap_item;
+
+static void heap_push(heap_item *h, int64_t *size, uint64_t d, int32_t v) {
+    int64_t i = (*size)++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= d) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i].d = d;
+    h[i].v = v;
+}
+
+static heap_item heap_pop(heap_item *h, int64_t *size) {
+    heap_item top = h[0];
+    heap_item last = h[--(*size)];
+    int64_t i = 0, n = *size;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, s = i;
+        uint64_t ds = last.d;
+        if (l < n && h[l].d < ds) { s = l; ds = h[l].d; }
+        if (r < n && h[r].d < ds) { s = r; }
+        if (s == i) break;
+        h[i] = h[s];
+        i = s;
+    }
+    if (n > 0) h[i] = last;
+    return top;
+}
+
+/* Binary-heap Dijkstra over CSR out-edges with uint32 weights.
+ * dist/parent: caller-owned host arrays of length n.  Distances are
+ * accumulated in 64 bits; returns the number of reached vertices, -1 on
+ * invalid arguments / allocation failure, -2 if a finite distance does not
+ * fit below the 0xFFFFFFFF sentinel (dist is then not written for it). */
+int64_t oracle_dijkstra(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                        const uint32_t *w, int32_t src, uint32_t *dist, int32_t *parent) {
+    if (n <= 0 || src < 0 || src >= n || !row_ptr || !col || !w || !dist) return -1;
+    int64_t m = row_ptr[n];
+    uint64_t *d64 = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    heap_item *heap = (heap_item *)malloc((size_t)(m + 1) * sizeof(heap_item));
+    if (!d64 || !heap) {
+        free(d64);
+        free(heap);
+        return -1;
+    }
+    const uint64_t UNSEEN = UINT64_MAX;
+    for (int32_t v = 0; v < n; ++v) {
+        d64[v] = UNSEEN;
+        if (parent) parent[v] = -1;
+    }
+    int64_t hs = 0;
+    d64[src] = 0;
+    if (parent) parent[src] = src;
+    heap_push(heap, &hs, 0, src);
+    while (hs > 0) {
+        heap_item it = heap_pop(heap, &hs);
+        int32_t u = it.v;
+        if (it.d > d64[u]) continue; /* stale entry */
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t v = col[e];
+            uint64_t nd = it.d + (uint64_t)w[e];
+            if (nd < d64[v]) {
+                d64[v] = nd;
+                if (parent) parent[v] = u;
+                heap_push(heap, &hs, nd, v);
+            }
+        }
+    }
+    int64_t reached = 0;
+    int overflow = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (d64[v] == UNSEEN) {
+            dist[v] = ORACLE_INF;
+        } else if (d64[v] >= (uint64_t)ORACLE_INF) {
+            overflow = 1;
+            dist[v] = ORACLE_INF;
+        } else {
+            dist[v] = (uint32_t)d64[v];
+            ++reached;
+        }
+    }
+    free(d64);
+    free(heap);
+    return overflow ? -2 : reached;
+}
+
+/* Sum of out-degrees of the vertices with level != INF: the number of CSR
+ * entries an exact top-down traversal from the source scans. */
+int64_t oracle_edges_scanned(int32_t n, const int32_t *row_ptr, const uint32_t *level) {
+    int64_t s = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (level[v] != ORACLE_INF) s += (int64_t)row_ptr[v + 1] - row_ptr[v];
+    return s;
+}
