@@ -1,0 +1,182 @@
+/*
+ * irgl.h -- C ABI of the MI355X data-driven BFS/SSSP library.
+ *
+ * The operation is the paper's level-by-level worklist BFS (Section 4.1,
+ * BFS listing; Iterate with an initial worklist [src], Section 4.2 and
+ * Table 1): pop every item of the incoming worklist, visit each out-edge of
+ * the popped vertex, label unvisited destinations with the next level and
+ * push them on the outgoing worklist; swap the worklists after every
+ * invocation and stop when the outgoing worklist is empty.  SSSP is the same
+ * data-driven loop with "distance improved" in place of "unvisited"
+ * (textbook single-source shortest paths; the paper states only BFS).
+ *
+ * Results are exact integers:
+ *   level[v] = least number of out-edges on a path src -> v,
+ *   dist[v]  = least sum of weights on a path src -> v,
+ * with IRGL_INF (0xFFFFFFFF) for unreachable vertices.
+ *
+ * Conventions for every entry point:
+ *   - Return value is an irgl_status; nothing throws across the ABI.
+ *   - "device pointer" means memory on the current HIP device (any
+ *     hipMalloc'd buffer, e.g. a torch tensor's data_ptr()); the library
+ *     never frees caller memory and allocates no device memory of its own.
+ *   - Query entry points are asynchronous on the given HIP stream (pass the
+ *     hipStream_t as void*; NULL = the null stream) and never synchronize
+ *     the host, except where stated.
+ *   - Errors found on the device (worklist overflow, distance overflow,
+ *     watchdog, abort, iteration limit) are written to the stats block; read
+ *     them with irgl_query_status() after the stream has completed.
+ *   - A graph handle is immutable after upload and may serve concurrent
+ *     queries that use distinct workspaces and outputs.
+ */
+#ifndef IRGL_H
+#define IRGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IRGL_VERSION 100 /* 0.1.0 */
+#define IRGL_INF 0xFFFFFFFFu
+
+typedef int32_t irgl_status;
+enum {
+    IRGL_OK = 0,
+    IRGL_ERR_INVALID_ARGUMENT = 1,   /* null pointer, src out of range, n <= 0, m >= 2^31 */
+    IRGL_ERR_NO_WEIGHTS = 2,         /* SSSP on a graph uploaded without weights */
+    IRGL_ERR_INVALID_GRAPH = 3,      /* IRGL_VALIDATE found a malformed CSR */
+    IRGL_ERR_WORKSPACE_TOO_SMALL = 4,
+    IRGL_ERR_OVERFLOW = 5,           /* worklist capacity or uint32 distance exceeded */
+    IRGL_ERR_ABORTED = 6,            /* the host abort flag was raised */
+    IRGL_ERR_BUSY = 7,               /* no free slot (batched / served queries) */
+    IRGL_ERR_TOO_LARGE = 8,          /* a request can never fit its memory budget */
+    IRGL_ERR_NO_DEVICE = 9,          /* no HIP device visible */
+    IRGL_ERR_DEVICE = 10,            /* a HIP call failed; see irgl_last_hip_error() */
+    IRGL_ERR_WATCHDOG = 11,          /* the grid barrier waited past its time limit */
+    IRGL_ERR_ITERATION_LIMIT = 12,   /* the loop reached max_iter with work left */
+    IRGL_ERR_CONFIG = 13,            /* unsupported block size / thresholds / grid */
+    IRGL_ERR_INTERNAL = 14           /* a device-side consistency check failed */
+};
+
+enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
+
+/* Graph flags. */
+#define IRGL_SYMMETRIC 1u /* informational: every edge has its reverse with equal weight */
+#define IRGL_VALIDATE 2u  /* check the CSR on the device during upload (synchronizes) */
+
+#define IRGL_WATCHDOG_IMMEDIATE 0xFFFFFFFFu
+
+/* Launch modes. */
+enum {
+    IRGL_MODE_PERSISTENT = 0, /* one cooperative launch; the Iterate loop runs on the
+                                 device with a grid-wide barrier between invocations
+                                 (iteration outlining, Section 4.3) */
+    IRGL_MODE_HOST_LOOP = 1   /* one launch per invocation, the host reads the worklist
+                                 size back after each (the un-outlined form); this mode
+                                 synchronizes the stream once per level */
+};
+
+/* A CSR graph: row_ptr int32[n+1] (monotone, row_ptr[0] = 0, row_ptr[n] = m),
+ * col int32[m] (destinations in [0, n)), w uint32[m] (weights >= 1) or NULL.
+ * All three are DEVICE pointers.  The handle borrows them: the caller keeps
+ * them alive and unchanged until irgl_graph_free(). */
+typedef struct irgl_csr {
+    int32_t n;
+    int64_t m;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint32_t *w;
+    uint32_t flags;
+} irgl_csr;
+
+typedef struct irgl_graph_s *irgl_graph;
+
+/* Tuning knobs; a zero field takes the library default.  Nested edge
+ * parallelism (Section 4.3) splits the popped vertices into three tiers by
+ * out-degree: >= t_block -> the whole workgroup strides the neighbour range,
+ * >= t_wave -> one 64-lane wavefront strides it, otherwise the remaining
+ * ranges of a workgroup are concatenated by a prefix sum in LDS and dealt to
+ * consecutive lanes. */
+typedef struct irgl_config {
+    int32_t block;        /* threads per workgroup: 256, 512 or 1024 (fixed-block kernels) */
+    int32_t t_wave;       /* wavefront tier threshold, >= 1 (default 64) */
+    int32_t t_block;      /* workgroup tier threshold, >= t_wave (default = block) */
+    int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
+    int32_t mode;         /* IRGL_MODE_* */
+    uint32_t max_iter;    /* safety cap on invocations (default n + 1) */
+    uint32_t wl_capacity; /* worklist capacity in items (default n); smaller values
+                             exist to exercise the overflow path */
+    uint32_t watchdog_ms; /* grid-barrier wait limit in ms (default 20000);
+                             IRGL_WATCHDOG_IMMEDIATE makes every wait time out at
+                             once, to exercise the watchdog path */
+    const volatile int32_t *abort_flag; /* HOST pinned memory or NULL; a nonzero value
+                             makes the running query stop with IRGL_ERR_ABORTED */
+} irgl_config;
+
+/* Per-query statistics, written by the device when the query ends. */
+typedef struct irgl_stats {
+    int32_t status;        /* irgl_status of the device-side run */
+    uint32_t iterations;   /* kernel invocations (BFS: max level + 1) */
+    uint64_t items;        /* worklist items popped, summed over invocations */
+    uint64_t edges;        /* CSR entries scanned */
+    uint32_t max_frontier; /* largest incoming worklist */
+    int32_t grid;          /* workgroups used */
+    int32_t block;         /* threads per workgroup used */
+    uint32_t reserved;
+} irgl_stats;
+
+int irgl_version(void);
+const char *irgl_status_string(irgl_status s);
+/* hipError_t of the last failed HIP call in this thread (0 if none). */
+int32_t irgl_last_hip_error(void);
+
+/* Register a device-resident CSR graph (Section 4.1: the graph whose
+ * edges(n) the BFS kernel iterates).  *out receives a handle that borrows the
+ * caller's arrays.  With IRGL_VALIDATE the CSR is checked on the device and
+ * the call synchronizes; a malformed graph gives IRGL_ERR_INVALID_GRAPH.
+ * Errors: INVALID_ARGUMENT (null csr/out/row_ptr, null col with m > 0,
+ * n <= 0, m < 0, m >= 2^31), NO_DEVICE, DEVICE. */
+irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out);
+
+/* Release a handle (not the arrays it borrows).  NULL is accepted. */
+irgl_status irgl_graph_free(irgl_graph g);
+
+/* Bytes of device workspace one query of `kind` needs on graph g with the
+ * given config (NULL = defaults).  The workspace holds the two worklists of
+ * the pipe context (Section 4.2: "in" and "out"), the loop's counters and
+ * barrier state, and for SSSP the per-vertex push stamps. */
+irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent,
+                                 const irgl_config *cfg, size_t *bytes);
+
+/* BFS levels from src (Section 4.1, level-by-level worklist BFS; the level
+ * of src is 0 and a vertex found while expanding level k gets k + 1).
+ * level: device uint32[n] (output).  parent: device int32[n] or NULL; when
+ * given, parent[src] = src, unreached = -1, otherwise a vertex p with an edge
+ * p -> v and level[p] + 1 == level[v] (not unique).  ws: device workspace of
+ * ws_bytes >= irgl_workspace_bytes(g, IRGL_KIND_BFS, ...).  dstats: device
+ * irgl_stats or NULL.  cfg: NULL = defaults. */
+irgl_status irgl_bfs(irgl_graph g, int32_t src, uint32_t *level, int32_t *parent, void *ws,
+                     size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_config *cfg);
+
+/* Single-source shortest paths from src by the same data-driven worklist
+ * loop (bulk-synchronous Bellman-Ford: a vertex whose distance improved is
+ * pushed once per invocation).  dist: device uint32[n] (output).  parent:
+ * device int32[n] or NULL; when given, parent[v] is the smallest vertex id p
+ * with an edge p -> v of weight w and dist[p] + w == dist[v] (deterministic).
+ * Requires weights (IRGL_ERR_NO_WEIGHTS otherwise).  A finite distance that
+ * does not fit below IRGL_INF ends the query with IRGL_ERR_OVERFLOW. */
+irgl_status irgl_sssp(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent, void *ws,
+                      size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_config *cfg);
+
+/* Synchronize `stream`, then copy the statistics of the last query that used
+ * workspace `ws` into host memory *out (status, iterations, counters). */
+irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRGL_H */

@@ -1,0 +1,310 @@
+"""Python binding of the C ABI in ``include/irgl.h`` (argument marshalling only).
+
+Every function named ``irgl_*`` here calls the C entry point of the same name
+in ``_lib/libirgl.so``; all graph work runs in that library's HIP kernels.
+Device memory and streams come from PyTorch: graph arrays, outputs and
+workspaces are CUDA (HIP) tensors, streams are ``torch.cuda.Stream`` objects.
+
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libirgl.so")
+
+INF = 0xFFFFFFFF
+
+IRGL_OK = 0
+IRGL_ERR_INVALID_ARGUMENT = 1
+IRGL_ERR_NO_WEIGHTS = 2
+IRGL_ERR_INVALID_GRAPH = 3
+IRGL_ERR_WORKSPACE_TOO_SMALL = 4
+IRGL_ERR_OVERFLOW = 5
+IRGL_ERR_ABORTED = 6
+IRGL_ERR_BUSY = 7
+IRGL_ERR_TOO_LARGE = 8
+IRGL_ERR_NO_DEVICE = 9
+IRGL_ERR_DEVICE = 10
+IRGL_ERR_WATCHDOG = 11
+IRGL_ERR_ITERATION_LIMIT = 12
+IRGL_ERR_CONFIG = 13
+IRGL_ERR_INTERNAL = 14
+
+IRGL_KIND_BFS = 0
+IRGL_KIND_SSSP = 1
+IRGL_SYMMETRIC = 1
+IRGL_VALIDATE = 2
+IRGL_MODE_PERSISTENT = 0
+IRGL_MODE_HOST_LOOP = 1
+IRGL_WATCHDOG_IMMEDIATE = 0xFFFFFFFF
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build() or python -m paper_1607_05707_amd._build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class irgl_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class irgl_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("t_wave", ctypes.c_int32), ("t_block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_uint32),
+                ("wl_capacity", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
+                ("abort_flag", ctypes.c_void_p)]
+
+
+class irgl_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_uint32),
+                ("items", ctypes.c_uint64), ("edges", ctypes.c_uint64),
+                ("max_frontier", ctypes.c_uint32), ("grid", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+STATS_BYTES = ctypes.sizeof(irgl_stats)
+
+_c = ctypes.c_void_p
+_lib.irgl_version.restype = ctypes.c_int
+_lib.irgl_version.argtypes = []
+_lib.irgl_status_string.restype = ctypes.c_char_p
+_lib.irgl_status_string.argtypes = [ctypes.c_int32]
+_lib.irgl_last_hip_error.restype = ctypes.c_int32
+_lib.irgl_last_hip_error.argtypes = []
+_lib.irgl_graph_upload.restype = ctypes.c_int32
+_lib.irgl_graph_upload.argtypes = [ctypes.POINTER(irgl_csr), ctypes.POINTER(_c)]
+_lib.irgl_graph_free.restype = ctypes.c_int32
+_lib.irgl_graph_free.argtypes = [_c]
+_lib.irgl_workspace_bytes.restype = ctypes.c_int32
+_lib.irgl_workspace_bytes.argtypes = [_c, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(irgl_config),
+                                      ctypes.POINTER(ctypes.c_size_t)]
+for _name in ("irgl_bfs", "irgl_sssp"):
+    _f = getattr(_lib, _name)
+    _f.restype = ctypes.c_int32
+    _f.argtypes = [_c, ctypes.c_int32, _c, _c, _c, ctypes.c_size_t, _c, _c, ctypes.POINTER(irgl_config)]
+_lib.irgl_query_status.restype = ctypes.c_int32
+_lib.irgl_query_status.argtypes = [_c, _c, ctypes.POINTER(irgl_stats)]
+
+
+class IrglError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = irgl_status_string(status)
+        if status == IRGL_ERR_DEVICE:
+            msg += f" (hipError {irgl_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]" if where else f"{msg} [{status}]")
+
+
+def _check(status: int, where: str) -> None:
+    if status != IRGL_OK:
+        raise IrglError(status, where)
+
+
+def irgl_version() -> int:
+    return int(_lib.irgl_version())
+
+
+def irgl_status_string(status: int) -> str:
+    return _lib.irgl_status_string(int(status)).decode()
+
+
+def irgl_last_hip_error() -> int:
+    return int(_lib.irgl_last_hip_error())
+
+
+def _dev_ptr(t: Optional[torch.Tensor], name: str, dtypes, numel: Optional[int] = None) -> Optional[int]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device (cuda) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+_I32 = (torch.int32, getattr(torch, "uint32", torch.int32))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_config(cfg=None) -> Optional[irgl_config]:
+    """dict / irgl_config / None -> irgl_config (zero fields take defaults)."""
+    if cfg is None or isinstance(cfg, irgl_config):
+        return cfg
+    c = irgl_config()
+    for k, v in dict(cfg).items():
+        if k == "abort_flag":
+            c.abort_flag = v if isinstance(v, int) or v is None else v.data_ptr()
+        else:
+            setattr(c, k, int(v))
+    return c
+
+
+def _cfg_ptr(cfg):
+    c = make_config(cfg)
+    return (ctypes.byref(c) if c is not None else None), c
+
+
+class Graph:
+    """A device-resident CSR graph registered with the library.
+
+    Holds references to the borrowed tensors for the handle's lifetime."""
+
+    def __init__(self, handle: int, n: int, m: int, row_ptr, col, w, flags: int):
+        self.handle = handle
+        self.n = n
+        self.m = m
+        self.row_ptr = row_ptr
+        self.col = col
+        self.w = w
+        self.flags = flags
+
+    @property
+    def weighted(self) -> bool:
+        return self.w is not None
+
+    def free(self) -> None:
+        if self.handle:
+            _lib.irgl_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def irgl_graph_upload(row_ptr: torch.Tensor, col: torch.Tensor, w: Optional[torch.Tensor] = None,
+                      flags: int = 0) -> Graph:
+    """Register a device CSR (int32 row_ptr[n+1], int32 col[m], uint32/int32 w[m] or None)."""
+    n = int(row_ptr.numel()) - 1
+    m = int(col.numel())
+    csr = irgl_csr()
+    csr.n = n
+    csr.m = m
+    csr.row_ptr = _dev_ptr(row_ptr, "row_ptr", _I32)
+    csr.col = _dev_ptr(col, "col", _I32) if m > 0 else None
+    csr.w = _dev_ptr(w, "w", _I32, m) if w is not None else None
+    csr.flags = int(flags)
+    h = ctypes.c_void_p()
+    _check(_lib.irgl_graph_upload(ctypes.byref(csr), ctypes.byref(h)), "irgl_graph_upload")
+    return Graph(h.value, n, m, row_ptr, col, w, flags)
+
+
+def irgl_graph_free(g: Graph) -> None:
+    g.free()
+
+
+def irgl_workspace_bytes(g: Graph, kind: int, with_parent: bool = False, cfg=None) -> int:
+    out = ctypes.c_size_t()
+    cp, _keep = _cfg_ptr(cfg)
+    _check(_lib.irgl_workspace_bytes(g.handle, int(kind), int(bool(with_parent)), cp, ctypes.byref(out)),
+           "irgl_workspace_bytes")
+    return int(out.value)
+
+
+def workspace(g: Graph, kind: int, with_parent: bool = False, cfg=None) -> torch.Tensor:
+    """Allocate a device workspace tensor of the size the library asks for."""
+    nbytes = irgl_workspace_bytes(g, kind, with_parent, cfg)
+    return torch.empty(nbytes, dtype=torch.uint8, device=g.row_ptr.device)
+
+
+def _run(fn, name, g: Graph, src: int, out: torch.Tensor, parent, ws, stream, stats, cfg) -> None:
+    if g.handle is None:
+        raise ValueError("graph handle was freed")
+    op = _dev_ptr(out, "out", _I32, g.n)
+    pp = _dev_ptr(parent, "parent", _I32, g.n)
+    if ws is None:
+        raise ValueError("a workspace tensor is required (see workspace())")
+    wp = _dev_ptr(ws, "ws", (torch.uint8,))
+    sp = _dev_ptr(stats, "stats", (torch.uint8,), STATS_BYTES) if stats is not None else None
+    cp, _keep = _cfg_ptr(cfg)
+    _check(fn(g.handle, int(src), op, pp, wp, ws.numel(), _stream_handle(stream), sp, cp), name)
+
+
+def irgl_bfs(g: Graph, src: int, level: torch.Tensor, parent: Optional[torch.Tensor] = None,
+             ws: Optional[torch.Tensor] = None, stream=None, stats: Optional[torch.Tensor] = None,
+             cfg=None) -> None:
+    """Asynchronous BFS from src on `stream`; level is a device int32/uint32 [n]."""
+    _run(_lib.irgl_bfs, "irgl_bfs", g, src, level, parent, ws, stream, stats, cfg)
+
+
+def irgl_sssp(g: Graph, src: int, dist: torch.Tensor, parent: Optional[torch.Tensor] = None,
+              ws: Optional[torch.Tensor] = None, stream=None, stats: Optional[torch.Tensor] = None,
+              cfg=None) -> None:
+    """Asynchronous SSSP from src on `stream`; dist is a device int32/uint32 [n]."""
+    _run(_lib.irgl_sssp, "irgl_sssp", g, src, dist, parent, ws, stream, stats, cfg)
+
+
+def irgl_query_status(ws: torch.Tensor, stream=None) -> dict:
+    """Synchronize `stream` and return the statistics of the workspace's last query."""
+    st = irgl_stats()
+    _check(_lib.irgl_query_status(_dev_ptr(ws, "ws", (torch.uint8,)), _stream_handle(stream),
+                                  ctypes.byref(st)), "irgl_query_status")
+    return st.as_dict()
+
+
+def stats_tensor(device) -> torch.Tensor:
+    """A zeroed device buffer for one irgl_stats."""
+    return torch.zeros(STATS_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_stats(buf: torch.Tensor) -> dict:
+    """Decode a device irgl_stats buffer (synchronizes through .cpu())."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    st = irgl_stats.from_buffer_copy(raw)
+    return st.as_dict()
+
+
+def as_u32_numpy(t: torch.Tensor):
+    """Device int32 tensor holding uint32 bits -> host numpy uint32."""
+    return t.cpu().numpy().view("uint32")
+
+
+# ---------------------------------------------------------------------------
+# Convenience: one synchronous query with freshly allocated outputs.
+# ---------------------------------------------------------------------------
+
+def query(g: Graph, kind: int, src: int, with_parent: bool = False, cfg=None, stream=None,
+          check: bool = True):
+    """Run one BFS/SSSP query and wait for it.  Returns (values, parent, stats)."""
+    dev = g.row_ptr.device
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    parent = torch.empty(g.n, dtype=torch.int32, device=dev) if with_parent else None
+    ws = workspace(g, kind, with_parent, cfg)
+    stats = stats_tensor(dev)
+    fn = irgl_bfs if kind == IRGL_KIND_BFS else irgl_sssp
+    fn(g, src, out, parent, ws, stream, stats, cfg)
+    if stream is not None:
+        stream.synchronize()
+    st = read_stats(stats)
+    if check and st["status"] != IRGL_OK:
+        raise IrglError(st["status"], "device")
+    return out, parent, st
+
+
+def upload(g, flags: int = IRGL_VALIDATE) -> Graph:
+    """Register a graphgen.CSRGraph whose tensors are already on the device."""
+    fl = flags | (IRGL_SYMMETRIC if getattr(g, "symmetric", False) else 0)
+    return irgl_graph_upload(g.row_ptr, g.col, g.w, fl)

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Levels and distances must match the oracle bit for bit; parents are not
+unique and are checked by the validator's invariants.  Sizes span several
+workgroup tiles with ragged tails, every nested-parallelism tier (by moving
+the tier thresholds), both launch modes and all block sizes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1607_05707_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+BFS, SSSP = 0, 1
+
+
+@pytest.fixture(scope="module")
+def irgl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1607_05707_amd import irgl as mod
+    return mod
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _check_query(irgl, g, hg, kind, src, cfg=None, with_parent=True, ref=None):
+    rp, col, w = g.numpy()
+    _say(f"{g.name} kind={kind} src={src} cfg={cfg}")
+    out, par, st = irgl.query(hg, kind, src, with_parent=with_parent, cfg=cfg)
+    got = irgl.as_u32_numpy(out)
+    if ref is None:
+        ref = oracle.bfs(rp, col, src)[0] if kind == BFS else oracle.dijkstra(rp, col, w, src)[0]
+    np.testing.assert_array_equal(got, ref, err_msg=f"{g.name} kind={kind} src={src} cfg={cfg}")
+    if with_parent:
+        oracle.validate(rp, col, src, got, par.cpu().numpy(), None if kind == BFS else w)
+    if kind == BFS:
+        assert st["iterations"] == int(ref[ref != oracle.INF].max()) + 1
+        assert st["edges"] == oracle.edges_scanned(rp, ref)
+        assert st["items"] == int((ref != oracle.INF).sum())
+    assert st["status"] == 0
+    return got, st
+
+
+def _dev(g):
+    return g.to(torch.device("cuda:0"))
+
+
+def test_grid64_all_blocks_and_modes(irgl):
+    g = _dev(gg.config_grid64())
+    hg = irgl.upload(g)
+    rp, col, w = g.numpy()
+    ref_l = oracle.bfs(rp, col, 0)[0]
+    ref_d = oracle.dijkstra(rp, col, w, 0)[0]
+    golden = np.loadtxt(__file__.replace("test_gpu_parity.py", "golden/grid64_levels_hist.txt"),
+                        dtype=np.int64)[:, 1]
+    for block in (256, 512, 1024):
+        for mode in (0, 1):
+            cfg = {"block": block, "mode": mode}
+            got, st = _check_query(irgl, g, hg, BFS, 0, cfg, ref=ref_l)
+            np.testing.assert_array_equal(oracle.level_histogram(got), golden)
+            assert st["iterations"] == 127
+            _check_query(irgl, g, hg, SSSP, 0, cfg, ref=ref_d)
+
+
+@pytest.mark.parametrize("t_wave,t_block", [(64, 512), (1, 1), (1, 4), (8, 64), (4096, 4096)])
+def test_rmat_tiers(irgl, t_wave, t_block):
+    g = _dev(gg.rmat(14, seed=3, weight_seed=4, wmax=255))
+    hg = irgl.upload(g)
+    cfg = {"t_wave": t_wave, "t_block": t_block}
+    for src in gg.pick_sources(g, 3, seed=5):
+        _check_query(irgl, g, hg, BFS, src, cfg)
+        _check_query(irgl, g, hg, SSSP, src, cfg)
+
+
+def test_tiny_random_graphs(irgl):
+    rng = np.random.default_rng(77)
+    for i in range(40):
+        n = int(rng.integers(1, 60))
+        m = int(rng.integers(0, 5 * n + 1))
+        g = _dev(gg.random_directed(n, m, seed=500 + i, weight_seed=600 + i, wmax=30))
+        hg = irgl.upload(g)
+        src = int(rng.integers(0, n))
+        _check_query(irgl, g, hg, BFS, src, {"block": 256})
+        _check_query(irgl, g, hg, SSSP, src, {"block": 256, "t_wave": 2, "t_block": 3})
+
+
+def test_star_hub_and_long_path(irgl):
+    n = 200_001
+    src = [0] * (n - 1) + list(range(1, n))
+    dst = list(range(1, n)) + [0] * (n - 1)
+    wts = list(range(1, n)) * 2
+    g = _dev(gg.from_edges(n, src, dst, wts, name="star"))
+    hg = irgl.upload(g)
+    _check_query(irgl, g, hg, BFS, 0)
+    _check_query(irgl, g, hg, BFS, 17)
+    _check_query(irgl, g, hg, SSSP, 5)
+    k = 20_000
+    w = np.random.default_rng(1).integers(1, 100, k - 1).tolist()
+    gp = _dev(gg.from_edges(k, list(range(k - 1)) + list(range(1, k)),
+                            list(range(1, k)) + list(range(k - 1)), w + w, name="path"))
+    hp = irgl.upload(gp)
+    _check_query(irgl, gp, hp, BFS, 0)
+    _check_query(irgl, gp, hp, SSSP, k // 3)
+
+
+def test_road_grid_small(irgl):
+    g = _dev(gg.config_road(width=256))
+    hg = irgl.upload(g)
+    for src in g.sources[:3]:
+        _check_query(irgl, g, hg, BFS, src)
+        _check_query(irgl, g, hg, SSSP, src)
+
+
+def test_isolated_source_and_single_vertex(irgl):
+    g = _dev(gg.from_edges(5, [0, 1], [1, 0], [3, 3], name="tiny"))
+    hg = irgl.upload(g)
+    _check_query(irgl, g, hg, BFS, 3)
+    _check_query(irgl, g, hg, SSSP, 4)
+    g1 = _dev(gg.from_edges(1, [], [], [], name="single"))
+    hg1 = irgl.upload(g1)
+    _check_query(irgl, g1, hg1, BFS, 0)
+
+
+def test_determinism_repeats(irgl):
+    g = _dev(gg.rmat(13, seed=9, weight_seed=10))
+    hg = irgl.upload(g)
+    rp, col, w = g.numpy()
+    src = gg.pick_sources(g, 1, seed=1)[0]
+    ref = oracle.dijkstra(rp, col, w, src)[0]
+    refp = None
+    for rep in range(10):
+        out, par, st = irgl.query(hg, SSSP, src, with_parent=True)
+        np.testing.assert_array_equal(irgl.as_u32_numpy(out), ref)
+        p = par.cpu().numpy()
+        if refp is None:
+            refp = p
+            oracle.validate(rp, col, src, ref, p, w)
+        np.testing.assert_array_equal(p, refp)  # SSSP parents are the smallest tight id
+
+
+def test_error_paths(irgl):
+    dev = torch.device("cuda:0")
+    g = _dev(gg.rmat(12, seed=1, weight_seed=2))
+    hg = irgl.upload(g)
+    src = gg.pick_sources(g, 1, seed=3)[0]
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ws = irgl.workspace(hg, SSSP)
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_bfs(hg, g.n, out, None, ws)
+    assert e.value.status == irgl.IRGL_ERR_INVALID_ARGUMENT
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_bfs(hg, src, out, None, ws[:1000])
+    assert e.value.status == irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_bfs(hg, src, out, None, ws, cfg={"block": 384})
+    assert e.value.status == irgl.IRGL_ERR_CONFIG
+    gu = irgl.irgl_graph_upload(g.row_ptr, g.col, None)
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_sssp(gu, src, out, None, ws)
+    assert e.value.status == irgl.IRGL_ERR_NO_WEIGHTS
+    # worklist overflow is reported, not written out of bounds
+    _say("overflow knob")
+    _, _, st = irgl.query(hg, BFS, src, cfg={"wl_capacity": 8}, check=False)
+    assert st["status"] == irgl.IRGL_ERR_OVERFLOW
+    # iteration limit
+    _, _, st = irgl.query(hg, BFS, src, cfg={"max_iter": 2}, check=False)
+    assert st["status"] == irgl.IRGL_ERR_ITERATION_LIMIT
+    _, _, st = irgl.query(hg, BFS, src, cfg={"max_iter": 2, "mode": 1}, check=False)
+    assert st["status"] == irgl.IRGL_ERR_ITERATION_LIMIT
+    # malformed CSR caught by on-device validation
+    bad_col = g.col.clone()
+    bad_col[5] = g.n + 3
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_graph_upload(g.row_ptr, bad_col, g.w, irgl.IRGL_VALIDATE)
+    assert e.value.status == irgl.IRGL_ERR_INVALID_GRAPH
+    # distance overflow
+    big = torch.full_like(g.w, 0x7FFFFFFF)
+    gb = irgl.irgl_graph_upload(g.row_ptr, g.col, big)
+    _say("distance overflow")
+    _, _, st = irgl.query(gb, SSSP, src, check=False)
+    assert st["status"] == irgl.IRGL_ERR_OVERFLOW
+
+
+def test_watchdog_and_abort_forced_from_host(irgl):
+    g = _dev(gg.grid2d(64))
+    hg = irgl.upload(g)
+    _say("watchdog immediate")
+    _, _, st = irgl.query(hg, BFS, 0, cfg={"watchdog_ms": irgl.IRGL_WATCHDOG_IMMEDIATE, "grid": 8},
+                          check=False)
+    assert st["status"] == irgl.IRGL_ERR_WATCHDOG
+    flag = torch.ones(1, dtype=torch.int32, pin_memory=True)
+    _say("abort flag")
+    _, _, st = irgl.query(hg, BFS, 0, cfg={"abort_flag": flag.data_ptr()}, check=False)
+    assert st["status"] == irgl.IRGL_ERR_ABORTED
+    # a cleared flag does not disturb the query
+    flag.zero_()
+    _check_query(irgl, g, hg, BFS, 0, {"abort_flag": flag.data_ptr()})
