@@ -68,6 +68,8 @@ enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
 #define IRGL_VALIDATE 2u  /* check the CSR on the device during upload (synchronizes) */
 
 #define IRGL_WATCHDOG_IMMEDIATE 0xFFFFFFFFu
+#define IRGL_BITMAP_NEVER 0xFFFFFFFFu
+#define IRGL_GRID_TIER_OFF (-1)
 
 /* Launch modes. */
 enum {
@@ -95,15 +97,19 @@ typedef struct irgl_csr {
 typedef struct irgl_graph_s *irgl_graph;
 
 /* Tuning knobs; a zero field takes the library default.  Nested edge
- * parallelism (Section 4.3) splits the popped vertices into three tiers by
- * out-degree: >= t_block -> the whole workgroup strides the neighbour range,
- * >= t_wave -> one 64-lane wavefront strides it, otherwise the remaining
- * ranges of a workgroup are concatenated by a prefix sum in LDS and dealt to
- * consecutive lanes. */
+ * parallelism (Section 4.3) splits the popped vertices into four tiers by
+ * out-degree: >= t_grid -> every workgroup of the grid takes an equal share
+ * of the range, >= t_block -> the whole workgroup strides the neighbour
+ * range, >= t_wave -> one 64-lane wavefront strides it, otherwise the
+ * remaining ranges of a workgroup are concatenated by a prefix sum in LDS and
+ * dealt to consecutive lanes. */
 typedef struct irgl_config {
     int32_t block;        /* threads per workgroup: 256, 512 or 1024 (fixed-block kernels) */
     int32_t t_wave;       /* wavefront tier threshold, >= 1 (default 64) */
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default = block) */
+    int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
+                             into equal chunks over all workgroups after a grid
+                             barrier (default 32 x block); IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
     int32_t mode;         /* IRGL_MODE_* */
     uint32_t max_iter;    /* safety cap on invocations (default n + 1) */
@@ -114,6 +120,16 @@ typedef struct irgl_config {
                              once, to exercise the watchdog path */
     const volatile int32_t *abort_flag; /* HOST pinned memory or NULL; a nonzero value
                              makes the running query stop with IRGL_ERR_ABORTED */
+    uint32_t t_bitmap;    /* BFS: incoming-worklist size at which the visited bitmap
+                             (a level-start snapshot used to skip visited
+                             destinations) is refreshed; default n / 64,
+                             IRGL_BITMAP_NEVER disables it */
+    uint32_t trace_len;   /* entries of `trace` */
+    uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
+                             Four words per invocation i at 4i: wall-clock tick at its
+                             start, incoming worklist size, edges scanned (persistent
+                             mode), vertices deferred to the grid tier; then the end
+                             tick at 4 x iterations */
 } irgl_config;
 
 /* Per-query statistics, written by the device when the query ends. */
@@ -132,6 +148,9 @@ int irgl_version(void);
 const char *irgl_status_string(irgl_status s);
 /* hipError_t of the last failed HIP call in this thread (0 if none). */
 int32_t irgl_last_hip_error(void);
+/* Wall-clock tick rate (kHz) of the device the calling thread uses, for
+ * converting `trace` entries to time. */
+irgl_status irgl_wallclock_khz(int32_t *khz);
 
 /* Register a device-resident CSR graph (Section 4.1: the graph whose
  * edges(n) the BFS kernel iterates).  *out receives a handle that borrows the
@@ -147,7 +166,8 @@ irgl_status irgl_graph_free(irgl_graph g);
 /* Bytes of device workspace one query of `kind` needs on graph g with the
  * given config (NULL = defaults).  The workspace holds the two worklists of
  * the pipe context (Section 4.2: "in" and "out"), the loop's counters and
- * barrier state, and for SSSP the per-vertex push stamps. */
+ * barrier state, for BFS a visited bitmap and for SSSP the per-vertex push
+ * stamps. */
 irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent,
                                  const irgl_config *cfg, size_t *bytes);
 

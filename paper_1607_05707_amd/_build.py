@@ -14,6 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libirgl.so")
+RUNNER = os.path.join(LIBDIR, "irgl_run")
 ARCH = os.environ.get("IRGL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["irgl.hip"]
@@ -41,6 +42,14 @@ def build(verbose: bool = False, extra=()) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # native runner over the C ABI (timing / profiling without Python)
+    rcmd = [hipcc(), "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+            os.path.join(CSRC, "irgl_run.cpp"), "-L", LIBDIR, "-lirgl",
+            "-Wl,-rpath,$ORIGIN", "-o", RUNNER + ".tmp"]
+    if verbose:
+        print(" ".join(rcmd), flush=True)
+    subprocess.check_call(rcmd)
+    os.replace(RUNNER + ".tmp", RUNNER)
     return LIB
 
 

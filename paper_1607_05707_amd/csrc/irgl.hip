@@ -80,12 +80,16 @@ struct Cfg {
     int block;
     int t_wave;
     int t_block;
+    int t_grid;
     int grid;  // 0 = co-resident limit
     int mode;
     uint32_t max_iter;
     uint32_t cap;
     uint32_t watchdog_ms;
     const volatile int32_t *abort_flag;
+    uint32_t t_bitmap;
+    uint32_t trace_len;
+    unsigned long long *trace;
 };
 
 irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
@@ -95,6 +99,11 @@ irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
     r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
     r.t_block = (c && c->t_block) ? c->t_block : r.block;
     if (r.t_wave < 1 || r.t_block < r.t_wave) return IRGL_ERR_CONFIG;
+    // grid tier: vertices with at least this many edges are split over all
+    // workgroups (IRGL_GRID_TIER_OFF disables it)
+    r.t_grid = (c && c->t_grid) ? c->t_grid : 8 * r.block * kU;
+    if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
+    if (r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block)) return IRGL_ERR_CONFIG;
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
     r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
@@ -104,12 +113,16 @@ irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
     r.cap = (c && c->wl_capacity) ? std::min(c->wl_capacity, n) : n;
     r.watchdog_ms = (c && c->watchdog_ms) ? c->watchdog_ms : 20000u;
     r.abort_flag = c ? c->abort_flag : nullptr;
+    r.t_bitmap = (c && c->t_bitmap) ? c->t_bitmap : std::max(1u, n / 64u);
+    r.trace_len = (c && c->trace) ? c->trace_len : 0u;
+    r.trace = (c && c->trace) ? reinterpret_cast<unsigned long long *>(c->trace) : nullptr;
     *out = r;
     return IRGL_OK;
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, total;
+    size_t ctrl, wl0, wl1, stamp, visited, hub_v, hub_base, total;
+    uint32_t hub_cap;
 };
 
 Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
@@ -118,7 +131,15 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
     L.wl0 = align_up(sizeof(Ctrl));
     L.wl1 = L.wl0 + align_up(static_cast<size_t>(c.cap) * 4);
     L.stamp = L.wl1 + align_up(static_cast<size_t>(c.cap) * 4);
-    L.total = L.stamp + (kind == IRGL_KIND_SSSP ? align_up(static_cast<size_t>(g->n) * 4) : 0);
+    L.visited = L.stamp + (kind == IRGL_KIND_SSSP ? align_up(static_cast<size_t>(g->n) * 4) : 0);
+    const bool bitmap = kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER;
+    L.hub_v = L.visited + (bitmap ? align_up((static_cast<size_t>(g->n) + 31) / 32 * 4) : 0);
+    // at most m / t_grid vertices have t_grid or more edges
+    L.hub_cap = c.t_grid > 0
+                    ? static_cast<uint32_t>(std::min<int64_t>(g->n, g->m / c.t_grid + 1))
+                    : 0u;
+    L.hub_base = L.hub_v + align_up(static_cast<size_t>(L.hub_cap) * 4);
+    L.total = L.hub_base + align_up(static_cast<size_t>(L.hub_cap) * 4);
     return L;
 }
 
@@ -200,6 +221,10 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
             p.it = it;
             hipLaunchKernelGGL((level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
             IRGL_HIP(hipGetLastError());
+            if (p.t_grid > 0) {
+                hipLaunchKernelGGL((hub_level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
+                IRGL_HIP(hipGetLastError());
+            }
             IRGL_HIP(hipMemcpyAsync(host, &p.ctrl->cnt[(it + 1) % 3], 4, hipMemcpyDeviceToHost, s));
             IRGL_HIP(hipStreamSynchronize(s));
             if (*host == 0) break;
@@ -252,6 +277,15 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.wl0 = reinterpret_cast<int32_t *>(base + L.wl0);
     p.wl1 = reinterpret_cast<int32_t *>(base + L.wl1);
     p.stamp = kind == IRGL_KIND_SSSP ? reinterpret_cast<uint32_t *>(base + L.stamp) : nullptr;
+    p.visited = (kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER)
+                    ? reinterpret_cast<uint32_t *>(base + L.visited) : nullptr;
+    p.t_bitmap = c.t_bitmap;
+    p.t_grid = c.t_grid;
+    p.hub_cap = L.hub_cap;
+    p.hub_v = reinterpret_cast<int32_t *>(base + L.hub_v);
+    p.hub_base = reinterpret_cast<uint32_t *>(base + L.hub_base);
+    p.trace_len = c.trace_len;
+    p.trace = c.trace;
     p.dstats = reinterpret_cast<Stats *>(dstats);
     p.cap = c.cap;
     p.max_iter = c.max_iter;
@@ -297,6 +331,22 @@ const char *irgl_status_string(irgl_status s) {
 }
 
 int32_t irgl_last_hip_error(void) { return g_last_hip_error; }
+
+irgl_status irgl_wallclock_khz(int32_t *khz) {
+    if (!khz) return IRGL_ERR_INVALID_ARGUMENT;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return IRGL_ERR_NO_DEVICE;
+    }
+    int dev = 0;
+    IRGL_HIP(hipGetDevice(&dev));
+    DeviceInfo di;
+    irgl_status st = device_info(dev, &di);
+    if (st) return st;
+    *khz = di.wallclock_khz;
+    return IRGL_OK;
+}
 
 irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     if (!csr || !out) return IRGL_ERR_INVALID_ARGUMENT;

@@ -28,7 +28,10 @@ struct alignas(128) Ctrl {
     // items, pushes through cnt[(it + 1) % 3] and clears cnt[(it + 2) % 3],
     // which nobody reads again before the next barrier has passed.
     uint32_t cnt[3];
-    uint32_t pad0[29];
+    uint32_t pad0a;
+    // rotating grid-tier counters, packed (deferred vertices << 40 | chunks)
+    unsigned long long hub[3];
+    uint32_t pad0[22];
     // line 1: barrier generation (the only word waiting workgroups poll)
     uint32_t bar_gen;
     uint32_t pad1[31];

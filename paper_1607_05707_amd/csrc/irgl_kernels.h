@@ -3,13 +3,19 @@
 //   * Frontier expansion: the outer ForAll over the incoming worklist
 //     (Section 3.1: consecutive items on consecutive lanes) with nested edge
 //     parallelism for the inner ForAll over graph.edges(n) (Sections 4.1 and
-//     4.3): workgroup / wavefront / prefix-sum-gather tiers by out-degree.
-//   * Relax operators: the BFS check-and-label of the Section 4.1 listing made
-//     exactly-once with a compare-and-swap; the SSSP "distance improved" test
-//     with atomicMin and a per-invocation push stamp.
+//     4.3).  Four tiers by out-degree: grid (all workgroups split the edge
+//     ranges of the largest vertices into equal chunks after a grid barrier),
+//     workgroup, wavefront, and a prefix-sum gather that deals the small
+//     ranges of a workgroup to consecutive lanes.  Every tier hands each lane
+//     U edges per round so that U independent memory chains are in flight.
+//   * Relax operators, written as phases over a lane's U edges (all loads of
+//     one phase are issued before any result is used): the BFS
+//     check-and-label of the Section 4.1 listing made exactly-once with a
+//     compare-and-swap, behind a visited-bitmap filter; the SSSP "distance
+//     improved" test with atomicMin and a per-invocation push stamp.
 //   * The outlined Iterate loop (Sections 4.2 and 4.3): one persistent,
-//     co-resident grid that runs every invocation, separated by the grid
-//     barrier, swapping the in/out worklists each time.
+//     co-resident grid runs every invocation, separated by the grid barrier,
+//     swapping the in/out worklists each time.
 //   * The un-outlined form: one launch per invocation.
 //   * Initialisation (the worklist initializer [src]) and the SSSP parent pass.
 #pragma once
@@ -19,24 +25,25 @@
 namespace irgl {
 
 constexpr int kQueueCap = 256;  // LDS staging entries per wavefront
+constexpr int kU = 4;           // edges per lane per round (memory-level parallelism)
 
 // Shared-memory layout of the frontier kernels for workgroup size B.
 template <int B>
 struct Smem {
     static constexpr int NW = B / kWave;
-    int gather_edge[B];      // edge index of each slot of the current gather window
-    int gather_owner[B];     // thread whose vertex owns that edge
-    int vtx[B];              // popped vertex of each thread
-    uint32_t vval[B];        // its per-vertex value (SSSP distance at pop)
-    int wsum[NW];            // per-wavefront degree sums for the workgroup scan
-    int fill[NW];            // per-wavefront queue fill at the workgroup drain
+    int gather_edge[B * kU];       // edge index of each slot of the current gather window
+    uint16_t gather_owner[B * kU]; // thread whose vertex owns that edge
+    int vtx[B];                    // popped vertex of each thread
+    uint32_t vval[B];              // its per-vertex value (SSSP distance at pop)
+    int wsum[NW];                  // per-wavefront degree sums for the workgroup scan
+    int fill[NW];                  // per-wavefront queue fill at the workgroup drain
     int queue[NW][kQueueCap];
-    int owner;               // workgroup-tier vertex owner
+    int owner;                     // workgroup-tier vertex owner
     int big_r0, big_r1, big_v;
     uint32_t big_val;
     uint32_t base;
     int flag;
-    uint32_t cnt_in;
+    int hub_h;                     // grid tier: first deferred vertex of this workgroup
 };
 
 struct Params {
@@ -49,36 +56,65 @@ struct Params {
     uint32_t *stamp;      // SSSP push stamps
     int32_t *wl0;
     int32_t *wl1;
+    int32_t *hub_v;       // grid tier: deferred vertices of the current invocation
+    uint32_t *hub_base;   // grid tier: first chunk of each deferred vertex
+    uint32_t hub_cap;
     Ctrl *ctrl;
     Stats *dstats;        // optional
     uint32_t cap;         // worklist capacity
     uint32_t max_iter;
     int32_t t_wave;
     int32_t t_block;
+    int32_t t_grid;       // 0 disables the grid tier
     int32_t src;
     uint32_t it;          // host-loop mode: the invocation to run
     unsigned long long wd_ticks;
     const volatile int32_t *abort_flag;
+    uint32_t *visited;    // BFS visited bitmap, ceil(n / 32) words
+    uint32_t t_bitmap;    // refresh the bitmap when the incoming worklist is this large
+    uint32_t trace_len;
+    unsigned long long *trace;
 };
 
 // ---------------------------------------------------------------------------
-// Relax operators.  relax() is called once per scanned edge e = (sv -> d);
-// it returns true when d must be pushed on the outgoing worklist.
+// Relax operators.  relax(e, d, sv, sval, act) receives U scanned edges
+// e[k] = (sv[k] -> d[k]) of this lane, act[k] marking the live ones, and
+// leaves act[k] true for each destination that must be pushed.
 // ---------------------------------------------------------------------------
 struct BfsOp {
     static constexpr bool kPush = true;
     uint32_t *level;
     int32_t *parent;
-    uint32_t next;  // label of vertices found in this invocation
+    const uint32_t *visited;  // bitmap: a set bit means "visited" (never a false positive)
+    uint32_t next;            // label of vertices found in this invocation
     __device__ __forceinline__ uint32_t vertex_value(int) const { return 0u; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
-    __device__ __forceinline__ bool relax(int, int d, int sv, uint32_t) const {
-        // A plain (possibly stale) load filters out most visited vertices;
-        // stale values can only read INF, and the CAS below decides.
-        if (level[d] != kInf) return false;
-        if (atomicCAS(&level[d], kInf, next) != kInf) return false;
-        if (parent) parent[d] = sv;
-        return true;
+    __device__ __forceinline__ void relax(const int (&)[kU], const int (&d)[kU], const int (&sv)[kU],
+                                          const uint32_t (&)[kU], bool (&act)[kU]) const {
+        // Cheapest filter first: the n/8-byte bitmap stays resident in L2.
+        // (visited is null when the bitmap is disabled: a uniform branch)
+        if (visited) {
+            uint32_t wd[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) wd[k] = act[k] ? visited[static_cast<uint32_t>(d[k]) >> 5] : 0u;
+#pragma unroll
+            for (int k = 0; k < kU; ++k) act[k] = act[k] && !(wd[k] & (1u << (d[k] & 31)));
+        }
+        // A plain (possibly stale) load of the level filters most of the rest;
+        // stale values can only read INF, and the CAS decides.
+        uint32_t lv[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) lv[k] = act[k] ? level[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && lv[k] == kInf;
+            if (act[k]) act[k] = atomicCAS(&level[d[k]], kInf, next) == kInf;
+        }
+        if (parent) {
+#pragma unroll
+            for (int k = 0; k < kU; ++k)
+                if (act[k]) parent[d[k]] = sv[k];
+        }
     }
 };
 
@@ -91,18 +127,36 @@ struct SsspOp {
     Ctrl *ctrl;
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
-    __device__ __forceinline__ bool relax(int e, int d, int, uint32_t dv) const {
-        const uint32_t nd = dv + w[e];
-        if (nd < dv || nd == kInf) {  // the sum does not fit below the INF sentinel
-            set_error(ctrl, kErrOverflow, false);
-            return false;
+    __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],
+                                          const uint32_t (&dv)[kU], bool (&act)[kU]) const {
+        uint32_t nd[kU], cur[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) nd[k] = act[k] ? w[e[k]] : 0u;
+        bool ovf = false;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const uint32_t s = dv[k] + nd[k];
+            const bool bad = act[k] && (s < dv[k] || s == kInf);  // does not fit below INF
+            ovf |= bad;
+            act[k] = act[k] && !bad;
+            nd[k] = s;
         }
-        if (nd >= dist[d]) return false;
-        const uint32_t old = atomicMin(&dist[d], nd);
-        if (nd >= old) return false;
+        if (ovf) set_error(ctrl, kErrOverflow, false);
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? dist[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && nd[k] < cur[k];
+            if (act[k]) act[k] = nd[k] < atomicMin(&dist[d[k]], nd[k]);
+        }
         // push d at most once per invocation
-        if (stamp[d] == it) return false;
-        return atomicExch(&stamp[d], it) != it;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? stamp[d[k]] : it;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && cur[k] != it;
+            if (act[k]) act[k] = atomicExch(&stamp[d[k]], it) != it;
+        }
     }
 };
 
@@ -116,26 +170,90 @@ struct SsspParentOp {
     int32_t src;
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t dv) const { return dv != kInf; }
-    __device__ __forceinline__ bool relax(int e, int d, int sv, uint32_t dv) const {
-        if (d != src && dv + w[e] == dist[d] && dv + w[e] >= dv)
-            atomicMin(reinterpret_cast<uint32_t *>(&parent[d]), static_cast<uint32_t>(sv));
-        return false;
+    __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&sv)[kU],
+                                          const uint32_t (&dv)[kU], bool (&act)[kU]) const {
+        uint32_t s[kU], cur[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) s[k] = act[k] ? dv[k] + w[e[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? dist[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            if (act[k] && d[k] != src && s[k] == cur[k] && s[k] >= dv[k])
+                atomicMin(reinterpret_cast<uint32_t *>(&parent[d[k]]), static_cast<uint32_t>(sv[k]));
+            act[k] = false;
+        }
     }
 };
 
+// Where one invocation's pushes go.
+struct Sink {
+    uint32_t *cnt_out;
+    int32_t *out;
+    uint32_t cap;
+    Ctrl *ctrl;
+};
+
+// Relax U edges of one lane and push the survivors (all 64 lanes call it).
+template <class Op>
+__device__ __forceinline__ void relax_and_push(const Op &op, const int32_t *__restrict__ col,
+                                               const int (&e)[kU], bool (&act)[kU], const int (&sv)[kU],
+                                               const uint32_t (&sval)[kU], WaveQueue<kQueueCap> &wq,
+                                               const Sink &sk) {
+    int d[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) d[k] = act[k] ? col[e[k]] : 0;
+    op.relax(e, d, sv, sval, act);
+    if (Op::kPush) {
+#pragma unroll
+        for (int k = 0; k < kU; ++k) wq.push(act[k], d[k], sk.cnt_out, sk.out, sk.cap, sk.ctrl);
+    }
+}
+
+// A group of `width` lanes (lane index `li` in it) strides the range
+// [r0, r1) of vertex sv, U edges per lane per round.  The trip count is
+// uniform across the group.
+template <class Op>
+__device__ __forceinline__ void stride_range(const Op &op, const int32_t *__restrict__ col, int r0,
+                                             int r1, int sv, uint32_t sval, int li, int width,
+                                             WaveQueue<kQueueCap> &wq, const Sink &sk) {
+    int svs[kU];
+    uint32_t svals[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+        svs[k] = sv;
+        svals[k] = sval;
+    }
+    for (int e0 = r0; e0 < r1; e0 += width * kU) {
+        int e[kU];
+        bool act[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            e[k] = e0 + k * width + li;
+            act[k] = e[k] < r1;
+        }
+        relax_and_push(op, col, e, act, svs, svals, wq, sk);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Nested-parallel expansion of one invocation's incoming worklist.
-// `in == nullptr` means the identity worklist 0..cnt_in-1.  Every thread of
-// every workgroup must call it (it synchronises the workgroup).
+// Phase A of one invocation: nested-parallel expansion of the incoming
+// worklist.  `in == nullptr` means the identity worklist 0..cnt_in-1.
+// Vertices of out-degree >= t_grid (t_grid > 0) are appended to the
+// grid-tier list (hub_v / hub_base, counted by *hub_ctr) instead of being
+// expanded here.  Every thread of every workgroup must call it (it
+// synchronises the workgroup).
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t cnt_in, uint32_t n,
                                        const int32_t *__restrict__ row_ptr,
                                        const int32_t *__restrict__ col, const Op &op, Smem<B> &sm,
-                                       WaveQueue<kQueueCap> &wq, uint32_t *cnt_out, int32_t *out,
-                                       uint32_t cap, Ctrl *ctrl, int t_wave, int t_block,
+                                       WaveQueue<kQueueCap> &wq, const Sink &sk, int t_wave,
+                                       int t_block, int t_grid, int32_t *hub_v, uint32_t *hub_base,
+                                       uint32_t hub_cap, unsigned long long *hub_ctr,
                                        unsigned long long &edges) {
     constexpr int NW = B / kWave;
+    constexpr int kChunk = B * kU;
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wid = tid / kWave;
@@ -148,7 +266,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         if (i < cnt_in) {
             v = in ? in[i] : static_cast<int>(i);
             if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
-                set_error(ctrl, kErrInternal, false);
+                set_error(sk.ctrl, kErrInternal, false);
                 v = -1;
             } else {
                 val = op.vertex_value(v);
@@ -160,6 +278,19 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         }
         int deg = r1 - r0;
         edges += static_cast<unsigned long long>(deg);
+
+        // Tier 0: defer the largest ranges to the grid-wide phase.
+        if (t_grid > 0 && deg >= t_grid) {
+            const unsigned long long chunks =
+                (static_cast<unsigned long long>(deg) + kChunk - 1) / kChunk;
+            const unsigned long long old = atomicAdd(hub_ctr, (1ull << 40) | chunks);
+            const uint32_t slot = static_cast<uint32_t>(old >> 40);
+            if (slot < hub_cap) {
+                hub_v[slot] = v;
+                hub_base[slot] = static_cast<uint32_t>(old & ((1ull << 40) - 1));
+                deg = 0;
+            }  // else: list full; the vertex is expanded here (cannot happen: cap >= m / t_grid + 1)
+        }
 
         // Tier 1: the whole workgroup strides one large neighbour range at a time.
         while (__syncthreads_or(deg >= t_block)) {
@@ -173,18 +304,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                 deg = 0;
             }
             __syncthreads();
-            const int b0 = sm.big_r0, b1 = sm.big_r1, bv = sm.big_v;
-            const uint32_t bval = sm.big_val;
-            for (int e0 = b0; e0 < b1; e0 += B) {
-                const int e = e0 + tid;
-                bool p = false;
-                int d = 0;
-                if (e < b1) {
-                    d = col[e];
-                    p = op.relax(e, d, bv, bval);
-                }
-                if (Op::kPush) wq.push(p, d, cnt_out, out, cap, ctrl);
-            }
+            stride_range(op, col, sm.big_r0, sm.big_r1, sm.big_v, sm.big_val, tid, B, wq, sk);
         }
 
         // Tier 2: one wavefront strides one medium neighbour range at a time.
@@ -197,16 +317,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             const int wv = __shfl(v, leader, kWave);
             const uint32_t wval = __shfl(val, leader, kWave);
             if (lane == leader) deg = 0;
-            for (int e0 = w0; e0 < w1; e0 += kWave) {
-                const int e = e0 + lane;
-                bool p = false;
-                int d = 0;
-                if (e < w1) {
-                    d = col[e];
-                    p = op.relax(e, d, wv, wval);
-                }
-                if (Op::kPush) wq.push(p, d, cnt_out, out, cap, ctrl);
-            }
+            stride_range(op, col, w0, w1, wv, wval, lane, kWave, wq, sk);
         }
 
         // Tier 3: concatenate the remaining small ranges of the workgroup with
@@ -224,31 +335,79 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             total += s;
         }
         const int excl = wpre + incl - deg;
-        for (int done = 0; done < total; done += B) {
+        for (int done = 0; done < total; done += kChunk) {
             const int lo = max(excl, done);
-            const int hi = min(excl + deg, done + B);
+            const int hi = min(excl + deg, done + kChunk);
             for (int k = lo; k < hi; ++k) {
                 sm.gather_edge[k - done] = r0 + (k - excl);
-                sm.gather_owner[k - done] = tid;
+                sm.gather_owner[k - done] = static_cast<uint16_t>(tid);
             }
             __syncthreads();
-            bool p = false;
-            int d = 0;
-            if (tid < total - done) {
-                const int e = sm.gather_edge[tid];
-                const int o = sm.gather_owner[tid];
-                d = col[e];
-                p = op.relax(e, d, sm.vtx[o], sm.vval[o]);
+            int e[kU], sv[kU];
+            uint32_t sval[kU];
+            bool act[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const int slot = k * B + tid;
+                act[k] = slot < total - done;
+                const int o = act[k] ? sm.gather_owner[slot] : 0;
+                e[k] = act[k] ? sm.gather_edge[slot] : 0;
+                sv[k] = sm.vtx[o];
+                sval[k] = sm.vval[o];
             }
-            if (Op::kPush) wq.push(p, d, cnt_out, out, cap, ctrl);
+            relax_and_push(op, col, e, act, sv, sval, wq, sk);
             __syncthreads();
         }
     }
 }
 
+// Phase B (grid tier): every workgroup takes an equal contiguous share of
+// the chunks of the deferred vertices (a chunk is B*U edges of one vertex;
+// hub_base[] is ascending because slots and chunk bases come from one
+// packed counter).  Called by all threads of every workgroup.
+template <int B, class Op>
+__device__ __forceinline__ void expand_hubs(uint32_t nhubs, uint32_t nchunks, const int32_t *hub_v,
+                                            const uint32_t *hub_base,
+                                            const int32_t *__restrict__ row_ptr,
+                                            const int32_t *__restrict__ col, const Op &op, Smem<B> &sm,
+                                            WaveQueue<kQueueCap> &wq, const Sink &sk) {
+    constexpr int kChunk = B * kU;
+    const unsigned long long G = gridDim.x;
+    const uint32_t lo = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(blockIdx.x) / G);
+    const uint32_t hi = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(blockIdx.x + 1) / G);
+    if (lo >= hi) return;  // uniform across the workgroup
+    if (threadIdx.x == 0) {
+        // the last deferred vertex whose first chunk is <= lo
+        uint32_t a = 0, b = nhubs;
+        while (b - a > 1) {
+            const uint32_t mid = (a + b) / 2;
+            if (hub_base[mid] <= lo) a = mid;
+            else b = mid;
+        }
+        sm.hub_h = static_cast<int>(a);
+    }
+    __syncthreads();
+    uint32_t h = static_cast<uint32_t>(sm.hub_h);
+    uint32_t c = lo;
+    while (c < hi && h < nhubs) {
+        const int v = hub_v[h];
+        const uint32_t cb = hub_base[h];
+        const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+        const uint32_t nch = static_cast<uint32_t>((r1 - r0 + kChunk - 1) / kChunk);
+        const uint32_t c_end = min(hi, cb + nch);
+        const int e_lo = r0 + static_cast<int>((c - cb) * kChunk);
+        const int e_hi = min(r1, r0 + static_cast<int>((c_end - cb) * kChunk));
+        const uint32_t val = op.vertex_value(v);
+        stride_range(op, col, e_lo, e_hi, v, val, threadIdx.x, B, wq, sk);
+        c = c_end;
+        ++h;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation: val = INF except val[src] = 0; parent = -1 except
-// parent[src] = src; stamps = INF; in = [src]; counters and stats cleared.
+// parent[src] = src; stamps = INF; bitmap = {src}; in = [src]; counters and
+// stats cleared.
 // ---------------------------------------------------------------------------
 __global__ void init_kernel(Params p, int with_stamp) {
     const uint32_t n = static_cast<uint32_t>(p.n);
@@ -257,12 +416,16 @@ __global__ void init_kernel(Params p, int with_stamp) {
         p.val[i] = s ? 0u : kInf;
         if (p.parent) p.parent[i] = s ? p.src : -1;
         if (with_stamp) p.stamp[i] = kInf;
+        if (p.visited && (i & 31u) == 0u)
+            p.visited[i >> 5] = (static_cast<uint32_t>(p.src) >> 5 == i >> 5)
+                                    ? (1u << (p.src & 31)) : 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Ctrl *c = p.ctrl;
         c->cnt[0] = 1;
         c->cnt[1] = 0;
         c->cnt[2] = 0;
+        for (int k = 0; k < 3; ++k) c->hub[k] = 0;
         c->bar_gen = 0;
         c->bar_top = 0;
         for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
@@ -281,13 +444,39 @@ template <class Op>
 __device__ __forceinline__ Op make_op(const Params &p, uint32_t it);
 
 template <>
-__device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it) {
-    return BfsOp{p.val, p.parent, it + 1};
+__device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it) {
+    return SsspOp{p.val, p.w, p.stamp, it, p.ctrl};
 }
 
 template <>
-__device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it) {
-    return SsspOp{p.val, p.w, p.stamp, it, p.ctrl};
+__device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it) {
+    return BfsOp{p.val, p.parent, p.visited, it + 1};
+}
+
+// Refresh the BFS visited bitmap from the level array: one ballot per 64
+// consecutive vertices, coalesced reads, one plain word store per 32
+// vertices.  Readers may see old or new words concurrently; both only ever
+// mark visited vertices, so any mix is a valid filter.
+__device__ __forceinline__ void refresh_bitmap(const Params &p) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const uint32_t v = base + threadIdx.x;
+        const bool vis = v < n && p.val[v] != kInf;
+        const unsigned long long m = __ballot(vis);
+        const int lane = lane_id();
+        const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
+        if (lane == 0 && v0 < n) p.visited[v0 >> 5] = static_cast<uint32_t>(m);
+        if (lane == 32 && v < n) p.visited[v >> 5] = static_cast<uint32_t>(m >> 32);
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void level_prologue(const Params &, uint32_t) {}
+
+template <>
+__device__ __forceinline__ void level_prologue<BfsOp>(const Params &p, uint32_t cnt_in) {
+    if (p.visited && cnt_in >= p.t_bitmap) refresh_bitmap(p);
 }
 
 // Write the control block's statistics to the caller's stats block.
@@ -305,8 +494,43 @@ __device__ __forceinline__ void publish_stats(const Params &p) {
     s->reserved = 0;
 }
 
+// Sum a per-thread counter over the workgroup and add it to *dst.
+template <int B>
+__device__ __forceinline__ void add_block_total(unsigned long long x, unsigned long long *dst) {
+    __shared__ unsigned long long s_total;
+    if (threadIdx.x == 0) s_total = 0;
+    __syncthreads();
+    atomicAdd(&s_total, x);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(dst, s_total);
+}
+
+// Trace of invocation `it` (only when a trace buffer is given): edges this
+// workgroup scanned, and the number of vertices deferred to the grid tier.
+__device__ __forceinline__ void trace_level(const Params &p, uint32_t it, unsigned long long edges,
+                                            const unsigned long long *hub_ctr) {
+    __shared__ unsigned long long s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    if (edges) atomicAdd(&s_sum, edges);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&p.trace[4 * it + 2], s_sum);
+        if (blockIdx.x == 0) p.trace[4 * it + 3] = hub_ctr[0] >> 40;
+    }
+}
+
+// Grid tier of invocation `it`: read the settled deferred-vertex counter.
+__device__ __forceinline__ void hub_counts(unsigned long long hc, uint32_t hub_cap, uint32_t &nh,
+                                           uint32_t &nchunks) {
+    nh = min(static_cast<uint32_t>(hc >> 40), hub_cap);
+    nchunks = static_cast<uint32_t>(hc & ((1ull << 40) - 1));
+}
+
 // ---------------------------------------------------------------------------
 // The outlined Iterate loop: one cooperative launch runs every invocation.
+// An invocation that deferred vertices to the grid tier has two barriers
+// (after phase A, after phase B); any other has one.
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __global__ __launch_bounds__(B) void persistent_kernel(Params p) {
@@ -333,27 +557,47 @@ __global__ __launch_bounds__(B) void persistent_kernel(Params p) {
         }
         items += cnt_in;
         max_frontier = max(max_frontier, cnt_in);
-        if (blockIdx.x == 0 && tid == 0) store_agent(&ctrl->cnt[(it + 2) % 3], 0u);
-        uint32_t *cnt_out = &ctrl->cnt[(it + 1) % 3];
+        if (blockIdx.x == 0 && tid == 0) {
+            store_agent(&ctrl->cnt[(it + 2) % 3], 0u);
+            __hip_atomic_store(&ctrl->hub[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (4 * it + 3 < p.trace_len) {
+                p.trace[4 * it] = wall_clock64();
+                p.trace[4 * it + 1] = cnt_in;
+                p.trace[4 * it + 2] = 0;
+                p.trace[4 * it + 3] = 0;
+            }
+        }
+        const unsigned long long edges_before = edges;
+        const Sink sk{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
+        unsigned long long *hub_ctr = &ctrl->hub[it % 3];
+        level_prologue<Op>(p, cnt_in);
         const Op op = make_op<Op>(p, it);
-        expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, wq, cnt_out, out, p.cap, ctrl,
-                      p.t_wave, p.t_block, edges);
-        block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, cnt_out, out, p.cap, ctrl);
+        expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, wq, sk,
+                      p.t_wave, p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, edges);
+        block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, sk.cnt_out, out, p.cap, ctrl);
         if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag)) break;
+        if (p.t_grid > 0) {
+            // uniform: every workgroup reads the same settled counter
+            uint32_t nh, nchunks;
+            hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
+                       nh, nchunks);
+            if (nh > 0) {
+                expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, wq, sk);
+                block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, sk.cnt_out, out, p.cap, ctrl);
+                if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag)) break;
+            }
+        }
+        if (4 * it + 3 < p.trace_len) trace_level(p, it, edges - edges_before, hub_ctr);
         const int32_t *t = in;
         in = out;
         out = const_cast<int32_t *>(t);
     }
 
     // statistics and completion
-    __shared__ unsigned long long s_edges;
-    if (tid == 0) s_edges = 0;
-    __syncthreads();
-    atomicAdd(&s_edges, edges);
-    __syncthreads();
+    add_block_total<B>(edges, &ctrl->edges);
     if (tid == 0) {
-        atomicAdd(&ctrl->edges, s_edges);
         if (blockIdx.x == 0) {
+            if (4 * it < p.trace_len) p.trace[4 * it] = wall_clock64();
             ctrl->iterations = it;
             ctrl->items = items;
             ctrl->max_frontier = max_frontier;
@@ -370,8 +614,10 @@ __global__ __launch_bounds__(B) void persistent_kernel(Params p) {
 }
 
 // ---------------------------------------------------------------------------
-// Un-outlined form: one launch per invocation `p.it`; the host reads the
-// outgoing count back and decides whether to launch the next one.
+// Un-outlined form: invocation `p.it` is one launch of level_kernel (phase
+// A) and one of hub_level_kernel (phase B, returns at once when nothing was
+// deferred); the host reads the outgoing count back after each invocation
+// and decides whether to launch the next one.
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __global__ __launch_bounds__(B) void level_kernel(Params p) {
@@ -386,38 +632,57 @@ __global__ __launch_bounds__(B) void level_kernel(Params p) {
     int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
     uint32_t cnt_in = ctrl->cnt[it % 3];
     if (cnt_in > p.cap) cnt_in = p.cap;
-    uint32_t *cnt_out = &ctrl->cnt[(it + 1) % 3];
-    const Op op = make_op<Op>(p, it);
-    expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, wq, cnt_out, out, p.cap, ctrl, p.t_wave,
-                  p.t_block, edges);
-    block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, cnt_out, out, p.cap, ctrl);
-    __shared__ unsigned long long s_edges;
-    if (tid == 0) s_edges = 0;
-    __syncthreads();
-    atomicAdd(&s_edges, edges);
-    __syncthreads();
-    if (tid == 0) {
-        atomicAdd(&ctrl->edges, s_edges);
-        if (blockIdx.x == 0) {
-            ctrl->cnt[(it + 2) % 3] = 0;
-            ctrl->iterations = it + 1;
-            ctrl->items += cnt_in;
-            ctrl->max_frontier = max(ctrl->max_frontier, cnt_in);
-            ctrl->grid = static_cast<int32_t>(gridDim.x);
-            ctrl->block = B;
-        }
+    const Sink sk{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
+    if (blockIdx.x == 0 && tid == 0 && 4 * it + 3 < p.trace_len) {
+        p.trace[4 * it] = wall_clock64();
+        p.trace[4 * it + 1] = cnt_in;
     }
+    level_prologue<Op>(p, cnt_in);
+    const Op op = make_op<Op>(p, it);
+    expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, wq, sk, p.t_wave,
+                  p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges);
+    block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, sk.cnt_out, out, p.cap, ctrl);
+    add_block_total<B>(edges, &ctrl->edges);
+    if (tid == 0 && blockIdx.x == 0) {
+        ctrl->cnt[(it + 2) % 3] = 0;
+        ctrl->hub[(it + 2) % 3] = 0;
+        ctrl->iterations = it + 1;
+        ctrl->items += cnt_in;
+        ctrl->max_frontier = max(ctrl->max_frontier, cnt_in);
+        ctrl->grid = static_cast<int32_t>(gridDim.x);
+        ctrl->block = B;
+    }
+}
+
+template <int B, class Op>
+__global__ __launch_bounds__(B) void hub_level_kernel(Params p) {
+    __shared__ Smem<B> sm;
+    const int wid = threadIdx.x / kWave;
+    Ctrl *ctrl = p.ctrl;
+    const uint32_t it = p.it;
+    uint32_t nh, nchunks;
+    hub_counts(ctrl->hub[it % 3], p.hub_cap, nh, nchunks);
+    if (nh == 0) return;  // uniform across the grid
+    WaveQueue<kQueueCap> wq{sm.queue[wid], 0};
+    int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
+    const Sink sk{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
+    const Op op = make_op<Op>(p, it);
+    expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, wq, sk);
+    block_drain<B, kQueueCap>(wq, sm.fill, &sm.base, sk.cnt_out, out, p.cap, ctrl);
 }
 
 // Host-loop epilogue and the iteration-limit check of the un-outlined form.
 __global__ void finish_kernel(Params p, int hit_limit) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t it = p.ctrl->iterations;
+        if (4 * it < p.trace_len) p.trace[4 * it] = wall_clock64();
         if (hit_limit) set_error(p.ctrl, kErrIterLimit, false);
         publish_stats(p);
     }
 }
 
-// SSSP parent pass over the identity worklist of all n vertices.
+// SSSP parent pass over the identity worklist of all n vertices (the grid
+// tier is off: ranges of every size are expanded in place).
 template <int B>
 __global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
     __shared__ Smem<B> sm;
@@ -425,8 +690,10 @@ __global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
     WaveQueue<kQueueCap> wq{sm.queue[wid], 0};
     unsigned long long edges = 0;
     const SsspParentOp op{p.val, p.w, p.parent, p.src};
-    expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, wq,
-                            nullptr, nullptr, 0u, p.ctrl, p.t_wave, p.t_block, edges);
+    const Sink sk{nullptr, nullptr, 0u, p.ctrl};
+    expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr,
+                            p.col, op, sm, wq, sk, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr,
+                            edges);
 }
 
 // On-device CSR validation: row_ptr[0] == 0, monotone, row_ptr[n] == m,

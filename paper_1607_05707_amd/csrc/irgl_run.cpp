@@ -1,0 +1,175 @@
+// irgl_run: native command-line runner of the C ABI (no Python in the
+// process), for timing and profiling BFS/SSSP queries on a CSR file written
+// by paper_1607_05707_amd.workloads.
+//
+//   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
+//                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
+//
+// Prints one line per kind: queries, mean microseconds per query (hipEvent
+// pairs around each call on one stream) and GTEPS (edges scanned by the BFS
+// from each source / time).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "irgl.h"
+
+#define CK(x)                                                                          \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) {                                                        \
+            std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+#define CI(x)                                                                          \
+    do {                                                                               \
+        irgl_status s_ = (x);                                                          \
+        if (s_ != IRGL_OK) {                                                           \
+            std::fprintf(stderr, "irgl error %s at line %d\n", irgl_status_string(s_), __LINE__); \
+            return 1;                                                                  \
+        }                                                                              \
+    } while (0)
+
+int main(int argc, char **argv) {
+    if (argc < 2) {
+        std::fprintf(stderr, "usage: %s FILE [options]\n", argv[0]);
+        return 2;
+    }
+    std::string kinds = "bfs,sssp";
+    int nsrc = 8, reps = 1, warmup = 1;
+    irgl_config cfg;
+    std::memset(&cfg, 0, sizeof(cfg));
+    for (int i = 2; i + 1 < argc; i += 2) {
+        std::string k = argv[i];
+        const char *v = argv[i + 1];
+        if (k == "--kinds") kinds = v;
+        else if (k == "--sources") nsrc = std::atoi(v);
+        else if (k == "--reps") reps = std::atoi(v);
+        else if (k == "--warmup") warmup = std::atoi(v);
+        else if (k == "--block") cfg.block = std::atoi(v);
+        else if (k == "--mode") cfg.mode = std::atoi(v);
+        else if (k == "--t-grid") cfg.t_grid = std::atoi(v);
+        else if (k == "--t-bitmap") cfg.t_bitmap = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else {
+            std::fprintf(stderr, "unknown option %s\n", k.c_str());
+            return 2;
+        }
+    }
+    FILE *f = std::fopen(argv[1], "rb");
+    if (!f) {
+        std::perror(argv[1]);
+        return 1;
+    }
+    char magic[8];
+    int64_t hdr[4];
+    if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "IRGLCSR1", 8) != 0 ||
+        std::fread(hdr, 8, 4, f) != 4) {
+        std::fprintf(stderr, "bad file header\n");
+        return 1;
+    }
+    const int64_t n = hdr[0], m = hdr[1], has_w = hdr[2], ns = hdr[3];
+    if (n <= 0 || n >= (int64_t(1) << 31) || m < 0 || m >= (int64_t(1) << 31) || ns <= 0) {
+        std::fprintf(stderr, "bad sizes\n");
+        return 1;
+    }
+    std::vector<int32_t> rp(n + 1), col(m), src(ns);
+    std::vector<uint32_t> w(has_w ? m : 0);
+    bool ok = std::fread(rp.data(), 4, n + 1, f) == static_cast<size_t>(n + 1) &&
+              std::fread(col.data(), 4, m, f) == static_cast<size_t>(m) &&
+              (!has_w || std::fread(w.data(), 4, m, f) == static_cast<size_t>(m)) &&
+              std::fread(src.data(), 4, ns, f) == static_cast<size_t>(ns);
+    std::fclose(f);
+    if (!ok) {
+        std::fprintf(stderr, "short file\n");
+        return 1;
+    }
+    if (nsrc > ns) nsrc = static_cast<int>(ns);
+
+    int32_t *d_rp, *d_col, *d_out;
+    uint32_t *d_w = nullptr;
+    CK(hipMalloc(&d_rp, (n + 1) * 4));
+    CK(hipMalloc(&d_col, m * 4 + 4));
+    CK(hipMalloc(&d_out, n * 4));
+    CK(hipMemcpy(d_rp, rp.data(), (n + 1) * 4, hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_col, col.data(), m * 4, hipMemcpyHostToDevice));
+    if (has_w) {
+        CK(hipMalloc(&d_w, m * 4 + 4));
+        CK(hipMemcpy(d_w, w.data(), m * 4, hipMemcpyHostToDevice));
+    }
+    irgl_csr csr{static_cast<int32_t>(n), m, d_rp, d_col, d_w, IRGL_VALIDATE};
+    irgl_graph g;
+    CI(irgl_graph_upload(&csr, &g));
+    irgl_stats *d_stats;
+    CK(hipMalloc(&d_stats, sizeof(irgl_stats)));
+    hipStream_t s;
+    CK(hipStreamCreate(&s));
+
+    std::vector<uint64_t> mcc(nsrc, 0);
+    for (int kind : {IRGL_KIND_BFS, IRGL_KIND_SSSP}) {
+        const char *name = kind == IRGL_KIND_BFS ? "bfs" : "sssp";
+        if (kinds.find(name) == std::string::npos && kind == IRGL_KIND_SSSP) continue;
+        if (kind == IRGL_KIND_SSSP && !has_w) continue;
+        size_t wsb = 0;
+        CI(irgl_workspace_bytes(g, kind, 0, &cfg, &wsb));
+        void *ws;
+        CK(hipMalloc(&ws, wsb));
+        auto run = [&](int32_t sv) {
+            return kind == IRGL_KIND_BFS ? irgl_bfs(g, sv, reinterpret_cast<uint32_t *>(d_out), nullptr, ws,
+                                                    wsb, s, d_stats, &cfg)
+                                         : irgl_sssp(g, sv, reinterpret_cast<uint32_t *>(d_out), nullptr, ws,
+                                                     wsb, s, d_stats, &cfg);
+        };
+        if (kind == IRGL_KIND_BFS) {  // numerator: edges scanned from each source
+            for (int i = 0; i < nsrc; ++i) {
+                CI(run(src[i]));
+                irgl_stats st;
+                CI(irgl_query_status(ws, s, &st));
+                if (st.status) {
+                    std::fprintf(stderr, "bfs from %d: %s\n", src[i], irgl_status_string(st.status));
+                    return 1;
+                }
+                mcc[i] = st.edges;
+            }
+        }
+        for (int r = 0; r < warmup; ++r)
+            for (int i = 0; i < nsrc; ++i) CI(run(src[i]));
+        std::vector<hipEvent_t> ev(2 * nsrc * reps);
+        for (auto &e : ev) CK(hipEventCreate(&e));
+        int k = 0;
+        for (int r = 0; r < reps; ++r)
+            for (int i = 0; i < nsrc; ++i) {
+                CK(hipEventRecord(ev[k++], s));
+                CI(run(src[i]));
+                CK(hipEventRecord(ev[k++], s));
+            }
+        CK(hipStreamSynchronize(s));
+        irgl_stats st;
+        CI(irgl_query_status(ws, s, &st));
+        double tot_ms = 0, edges = 0;
+        for (int q = 0; q < nsrc * reps; ++q) {
+            float ms;
+            CK(hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
+            tot_ms += ms;
+            edges += static_cast<double>(mcc[q % nsrc]);
+        }
+        std::printf("%s queries=%d mean_us=%.1f gteps=%.3f status=%d iterations=%u grid=%dx%d\n", name,
+                    nsrc * reps, 1e3 * tot_ms / (nsrc * reps), edges / (tot_ms * 1e-3) / 1e9, st.status,
+                    st.iterations, st.grid, st.block);
+        std::fflush(stdout);
+        for (auto &e : ev) CK(hipEventDestroy(e));
+        CK(hipFree(ws));
+    }
+    CI(irgl_graph_free(g));
+    CK(hipStreamDestroy(s));
+    CK(hipFree(d_stats));
+    CK(hipFree(d_rp));
+    CK(hipFree(d_col));
+    CK(hipFree(d_out));
+    if (d_w) CK(hipFree(d_w));
+    return 0;
+}

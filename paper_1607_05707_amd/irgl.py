@@ -43,6 +43,8 @@ IRGL_VALIDATE = 2
 IRGL_MODE_PERSISTENT = 0
 IRGL_MODE_HOST_LOOP = 1
 IRGL_WATCHDOG_IMMEDIATE = 0xFFFFFFFF
+IRGL_BITMAP_NEVER = 0xFFFFFFFF
+IRGL_GRID_TIER_OFF = -1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
@@ -57,9 +59,10 @@ class irgl_csr(ctypes.Structure):
 
 class irgl_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("t_wave", ctypes.c_int32), ("t_block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_uint32),
+                ("t_grid", ctypes.c_int32), ("grid", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_uint32),
                 ("wl_capacity", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
-                ("abort_flag", ctypes.c_void_p)]
+                ("abort_flag", ctypes.c_void_p), ("t_bitmap", ctypes.c_uint32),
+                ("trace_len", ctypes.c_uint32), ("trace", ctypes.c_void_p)]
 
 
 class irgl_stats(ctypes.Structure):
@@ -92,6 +95,8 @@ for _name in ("irgl_bfs", "irgl_sssp"):
     _f = getattr(_lib, _name)
     _f.restype = ctypes.c_int32
     _f.argtypes = [_c, ctypes.c_int32, _c, _c, _c, ctypes.c_size_t, _c, _c, ctypes.POINTER(irgl_config)]
+_lib.irgl_wallclock_khz.restype = ctypes.c_int32
+_lib.irgl_wallclock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
 _lib.irgl_query_status.restype = ctypes.c_int32
 _lib.irgl_query_status.argtypes = [_c, _c, ctypes.POINTER(irgl_stats)]
 
@@ -120,6 +125,12 @@ def irgl_status_string(status: int) -> str:
 
 def irgl_last_hip_error() -> int:
     return int(_lib.irgl_last_hip_error())
+
+
+def irgl_wallclock_khz() -> int:
+    out = ctypes.c_int32()
+    _check(_lib.irgl_wallclock_khz(ctypes.byref(out)), "irgl_wallclock_khz")
+    return int(out.value)
 
 
 def _dev_ptr(t: Optional[torch.Tensor], name: str, dtypes, numel: Optional[int] = None) -> Optional[int]:
@@ -153,8 +164,8 @@ def make_config(cfg=None) -> Optional[irgl_config]:
         return cfg
     c = irgl_config()
     for k, v in dict(cfg).items():
-        if k == "abort_flag":
-            c.abort_flag = v if isinstance(v, int) or v is None else v.data_ptr()
+        if k in ("abort_flag", "trace"):
+            setattr(c, k, v if isinstance(v, int) or v is None else v.data_ptr())
         else:
             setattr(c, k, int(v))
     return c

@@ -68,11 +68,12 @@ def test_grid64_all_blocks_and_modes(irgl):
             _check_query(irgl, g, hg, SSSP, 0, cfg, ref=ref_d)
 
 
-@pytest.mark.parametrize("t_wave,t_block", [(64, 512), (1, 1), (1, 4), (8, 64), (4096, 4096)])
-def test_rmat_tiers(irgl, t_wave, t_block):
+@pytest.mark.parametrize("t_wave,t_block,t_bitmap", [(64, 512, 0), (1, 1, 0), (1, 4, 1), (8, 64, 0),
+                                                   (4096, 4096, 0), (64, 512, 0xFFFFFFFF)])
+def test_rmat_tiers(irgl, t_wave, t_block, t_bitmap):
     g = _dev(gg.rmat(14, seed=3, weight_seed=4, wmax=255))
     hg = irgl.upload(g)
-    cfg = {"t_wave": t_wave, "t_block": t_block}
+    cfg = {"t_wave": t_wave, "t_block": t_block, "t_bitmap": t_bitmap}
     for src in gg.pick_sources(g, 3, seed=5):
         _check_query(irgl, g, hg, BFS, src, cfg)
         _check_query(irgl, g, hg, SSSP, src, cfg)
