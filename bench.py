@@ -89,6 +89,70 @@ def cpu_baseline(g, sources, budget_s: float, gpu_results):
     }, parity
 
 
+def batched_section(args, dev):
+    """The batched workload (seed 256: uniform graphs of uneven size, BFS/SSSP
+    alternating, plus R-MAT scale 20 with 64 BFS sources) in ONE persistent
+    launch, against the same queries each in its own launch ("plain")."""
+    import torch
+    from paper_1607_05707_amd import autotune, irgl
+    t0 = time.perf_counter()
+    keep, tasks = autotune.batch_tasks(256, args.batch_count, dev)
+    torch.cuda.synchronize()
+    log(f"batched workload: {len(tasks)} tasks, generated in {time.perf_counter() - t0:.1f}s")
+    # numerator per task: m_cc from an untimed BFS from the same source
+    mcc = []
+    for hg, kind, src in tasks:
+        _, _, st = irgl.query(hg, 0, src)
+        mcc.append(st["edges"])
+    cfg = autotune.load("batch")
+    t_batch = autotune.time_batch(tasks, cfg, reps=2)
+    # plain: one launch per query, back to back on one stream
+    outs = {}
+    wss = {}
+    for hg, kind, src in tasks:
+        key = (id(hg), kind)
+        if key not in wss:
+            wss[key] = irgl.workspace(hg, kind)
+            outs[id(hg)] = torch.empty(hg.n, dtype=torch.int32, device=dev)
+    best_plain = float("inf")
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for hg, kind, src in tasks:
+            fn = irgl.irgl_bfs if kind == 0 else irgl.irgl_sssp
+            fn(hg, src, outs[id(hg)], None, wss[(id(hg), kind)])
+        torch.cuda.synchronize()
+        best_plain = min(best_plain, time.perf_counter() - t0)
+    total = float(sum(mcc))
+    log(f"batched {t_batch * 1e3:.1f} ms vs plain {best_plain * 1e3:.1f} ms")
+    return {"tasks": len(tasks), "config": cfg, "batched_ms": round(t_batch * 1e3, 2),
+            "plain_ms": round(best_plain * 1e3, 2), "speedup": round(best_plain / t_batch, 3),
+            "batched_gteps": round(total / t_batch / 1e9, 3), "plain_gteps": round(total / best_plain / 1e9, 3)}
+
+
+def served_section(args, dev):
+    """Continuous batching over the eight resident graphs at a fixed fraction
+    of the plain capacity: p50/p99 latency and throughput, served vs plain."""
+    import numpy as np
+    from paper_1607_05707_amd import autotune, serve
+    t0 = time.perf_counter()
+    graphs = serve.resident_set("full", dev)
+    log(f"served set resident in {time.perf_counter() - t0:.1f}s")
+    cap_q = serve.query_stream(graphs, 200, 6)
+    capacity = serve.measure_capacity(graphs, cap_q)
+    queries = serve.query_stream(graphs, args.serve_queries, 5)
+    arr = serve.poisson_arrivals(len(queries), args.serve_lambda * capacity, 12)
+    cfg = autotune.load("serve")
+    lat_s, wall_s, _, rej = serve.run_served(graphs, queries, arr, 4 << 30, cfg={"team": cfg.get("team", 16),
+                                                                                  "block": cfg.get("block", 256)})
+    lat_p, wall_p = serve.run_plain(graphs, queries, arr)
+    out = {"graphs": len(graphs), "queries": len(queries), "lambda_frac": args.serve_lambda,
+           "plain_capacity_qps": round(capacity, 1), "budget_gb": 4, "rejected": rej,
+           "served": serve.summarize(lat_s, wall_s), "plain": serve.summarize(lat_p, wall_p)}
+    log(f"served {out['served']} plain {out['plain']}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +170,11 @@ def main() -> int:
     ap.add_argument("--mode", default="persistent", choices=["persistent", "hostloop"])
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-lambda", type=float, default=0.8)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -227,6 +296,13 @@ def main() -> int:
         log("timing the CPU oracle on a bounded sample")
         cpu, parity = cpu_baseline(g, sources, args.cpu_budget, gpu_results)
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_section(args, dev)
+    served = None
+    if not args.no_served:
+        served = served_section(args, dev)
+
     names = {0: "bfs", 1: "sssp"}
     line = {
         "metric": "GTEPS BFS/SSSP on RMAT-22, batched vs plain; HBM GB/s; p99 query latency",
@@ -255,6 +331,8 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -70,6 +70,7 @@ enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
 #define IRGL_WATCHDOG_IMMEDIATE 0xFFFFFFFFu
 #define IRGL_BITMAP_NEVER 0xFFFFFFFFu
 #define IRGL_GRID_TIER_OFF (-1)
+#define IRGL_DELTA_NONE 0xFFFFFFFFu
 
 /* Launch modes. */
 enum {
@@ -109,10 +110,11 @@ typedef struct irgl_config {
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default = block) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
-                             barrier (default 32 x block); IRGL_GRID_TIER_OFF = never */
+                             barrier (default 8 x block); IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
     int32_t mode;         /* IRGL_MODE_* */
-    uint32_t max_iter;    /* safety cap on invocations (default n + 1) */
+    uint32_t max_iter;    /* safety cap on invocations (default n + 1 for BFS,
+                             4n + 16 for SSSP, whose threshold raises also count) */
     uint32_t wl_capacity; /* worklist capacity in items (default n); smaller values
                              exist to exercise the overflow path */
     uint32_t watchdog_ms; /* grid-barrier wait limit in ms (default 20000);
@@ -125,6 +127,12 @@ typedef struct irgl_config {
                              destinations) is refreshed; default n / 64,
                              IRGL_BITMAP_NEVER disables it */
     uint32_t trace_len;   /* entries of `trace` */
+    uint32_t delta;       /* SSSP: near/far threshold step.  Distances below the
+                             threshold are expanded in bulk-synchronous invocations;
+                             larger ones wait on a far list until the threshold has
+                             risen past them.  0 = 8 x mean weight / mean degree when
+                             the graph was uploaded with IRGL_VALIDATE, otherwise
+                             IRGL_DELTA_NONE (plain Bellman-Ford order) */
     uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
                              Four words per invocation i at 4i: wall-clock tick at its
                              start, incoming worklist size, edges scanned (persistent
@@ -167,7 +175,7 @@ irgl_status irgl_graph_free(irgl_graph g);
  * given config (NULL = defaults).  The workspace holds the two worklists of
  * the pipe context (Section 4.2: "in" and "out"), the loop's counters and
  * barrier state, for BFS a visited bitmap and for SSSP the per-vertex push
- * stamps. */
+ * stamps, the two far lists and far flags. */
 irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent,
                                  const irgl_config *cfg, size_t *bytes);
 
@@ -194,6 +202,97 @@ irgl_status irgl_sssp(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent
 /* Synchronize `stream`, then copy the statistics of the last query that used
  * workspace `ws` into host memory *out (status, iterations, counters). */
 irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out);
+
+/* ---------------------------------------------------------------------
+ * Batched queries: many BFS/SSSP instances, of uneven graph sizes and
+ * sources, in ONE persistent cooperative launch fed from a device-resident
+ * task queue.  The grid is split into teams of `team` workgroups; each team
+ * repeatedly takes the next task (largest first), runs the outlined Iterate
+ * loop of Section 4.3 on it with its own barrier and scratch, and writes the
+ * task's statistics.  The control kernel holds both loop bodies, so its
+ * workgroup size is taken from T_control = T_BFS ∩ T_SSSP (Section 4.3);
+ * irgl_control_block_sizes() reports that set.
+ * --------------------------------------------------------------------- */
+typedef struct irgl_task {
+    irgl_graph g;
+    int32_t kind;      /* IRGL_KIND_BFS or IRGL_KIND_SSSP */
+    int32_t src;
+    uint32_t *out;     /* device uint32[n] (levels or distances) */
+    int32_t *parent;   /* device int32[n] or NULL (same meaning as irgl_bfs/irgl_sssp) */
+    uint64_t tag;      /* caller's cookie, not interpreted */
+} irgl_task;
+
+typedef struct irgl_batch_config {
+    int32_t block;     /* workgroup size, a member of T_control (default 256) */
+    int32_t team;      /* workgroups per team (default 16; clamped to the grid) */
+    int32_t t_wave;    /* tier thresholds as in irgl_config (0 = defaults) */
+    int32_t t_block;
+    int32_t t_grid;
+    uint32_t delta;    /* SSSP near/far step for every task (0 = per-graph default) */
+    uint32_t watchdog_ms;
+    int32_t grid;      /* workgroups (0 = co-resident limit); rounded down to whole teams */
+} irgl_batch_config;
+
+typedef struct irgl_batch_s *irgl_batch;
+
+/* Workgroup sizes usable by the batched control kernel (T_control).  Writes
+ * up to `cap` sizes, ascending, to sizes[] and their count to *count. */
+irgl_status irgl_control_block_sizes(int32_t *sizes, int32_t cap, int32_t *count);
+
+/* Device workspace bytes for a batch of `ntasks` host-described tasks. */
+irgl_status irgl_batch_workspace_bytes(const irgl_task *tasks, int32_t ntasks,
+                                       const irgl_batch_config *cfg, size_t *bytes);
+
+/* Launch the batch asynchronously on `stream`.  tasks: HOST array, read
+ * during the call.  ws: device workspace.  *out receives a handle for
+ * irgl_batch_wait / irgl_batch_free.  Errors: INVALID_ARGUMENT (bad task,
+ * ntasks <= 0), NO_WEIGHTS, WORKSPACE_TOO_SMALL, CONFIG, DEVICE. */
+irgl_status irgl_batch_submit(const irgl_task *tasks, int32_t ntasks, void *ws, size_t ws_bytes,
+                              const irgl_batch_config *cfg, void *stream, irgl_batch *out);
+
+/* Wait for the batch (synchronizes its stream) and copy each task's
+ * statistics, in task order, to per_task (HOST irgl_stats[ntasks], or NULL).
+ * Returns IRGL_OK when the launch completed; per-task device errors are in
+ * per_task[i].status. */
+irgl_status irgl_batch_wait(irgl_batch b, irgl_stats *per_task);
+
+/* Release the handle (waits for the batch first). */
+irgl_status irgl_batch_free(irgl_batch b);
+
+/* ---------------------------------------------------------------------
+ * Open batches (serving): the teams of a persistent server kernel take
+ * tasks from a ring in host pinned memory WHILE the kernel runs, so a
+ * request that arrives while others are on the GPU starts as soon as a team
+ * is free and overlaps them (continuous batching).  The kernel ends a team
+ * after `idle_ms` without work (or at close); irgl_batch_enqueue and
+ * irgl_batch_poll relaunch it when work is pending.  Calls on one server
+ * must come from one host thread.
+ * --------------------------------------------------------------------- */
+typedef struct irgl_server_s *irgl_server;
+
+/* Device workspace bytes of a server able to run tasks on any of graphs[]. */
+irgl_status irgl_batch_open_bytes(const irgl_graph *graphs, int32_t ngraphs,
+                                  const irgl_batch_config *cfg, int32_t ring_cap, size_t *bytes);
+
+/* Create a server (launches nothing yet).  graphs[]: every graph a task may
+ * use (scratch is sized for the largest).  ring_cap: descriptors in flight
+ * (queued or running) at most.  ws: device workspace of at least
+ * irgl_batch_open_bytes(...).  The server owns small pinned host buffers. */
+irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irgl_batch_config *cfg,
+                            int32_t ring_cap, uint32_t idle_ms, void *ws, size_t ws_bytes, void *stream,
+                            irgl_server *out);
+
+/* Queue one task; *ticket identifies it.  IRGL_ERR_BUSY when ring_cap tasks
+ * are in flight (retry after polling).  Asynchronous. */
+irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *ticket);
+
+/* *done = 1 and *st = the task's statistics when the task has finished (its
+ * outputs are then visible to the host and other streams), else *done = 0.
+ * Relaunches the server kernel if it has ended with work pending. */
+irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int32_t *done);
+
+/* Stop the server kernel, wait for it and release the handle. */
+irgl_status irgl_batch_close(irgl_server s);
 
 #ifdef __cplusplus
 }

@@ -12,15 +12,44 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "irgl.h"
 #include "irgl_kernels.h"
+#include "irgl_batch.h"
 
 using namespace irgl;
 
 static_assert(sizeof(Stats) == sizeof(irgl_stats), "irgl_stats layout");
 static_assert(offsetof(Stats, edges) == offsetof(irgl_stats, edges), "irgl_stats layout");
 static_assert(offsetof(Stats, block) == offsetof(irgl_stats, block), "irgl_stats layout");
+
+struct irgl_batch_s {
+    int32_t ntasks;
+    hipStream_t stream;
+    hipEvent_t done;
+    void *host_tasks;   // pinned staging of the task table
+    Stats *dev_stats;   // per-task statistics in the workspace
+    bool waited;
+};
+
+struct irgl_server_s {
+    int device;
+    hipStream_t stream;
+    hipEvent_t ran;          // recorded after each server launch
+    bool launched;
+    int block, grid;
+    irgl_batch_config cfg;
+    uint32_t delta;
+    int32_t ring_cap;
+    uint64_t next_ticket;
+    uint32_t *dev_head;      // device: claimed descriptors
+    Stats *dev_stats;        // device: per ring slot statistics
+    bool sssp_ok;            // scratch includes the SSSP arrays
+    int64_t mmax;            // largest graph the scratch was sized for (edges)
+    void *host_mem;          // pinned: ring | tail | stop | done[] | stats[]
+    void *params;            // ServerParams (host copy reused for launches)
+};
 
 struct irgl_graph_s {
     int32_t n;
@@ -30,6 +59,7 @@ struct irgl_graph_s {
     const uint32_t *w;
     uint32_t flags;
     int device;
+    uint64_t weight_sum;  // from IRGL_VALIDATE, else 0
 };
 
 namespace {
@@ -49,6 +79,8 @@ irgl_status hip_fail(hipError_t e) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+// default SSSP near/far step = kDeltaScale x mean weight / mean degree
+constexpr double kDeltaScale = 8.0;
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Per-device facts, looked up once.
@@ -90,6 +122,7 @@ struct Cfg {
     uint32_t t_bitmap;
     uint32_t trace_len;
     unsigned long long *trace;
+    uint32_t delta;
 };
 
 irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
@@ -101,7 +134,7 @@ irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
     if (r.t_wave < 1 || r.t_block < r.t_wave) return IRGL_ERR_CONFIG;
     // grid tier: vertices with at least this many edges are split over all
     // workgroups (IRGL_GRID_TIER_OFF disables it)
-    r.t_grid = (c && c->t_grid) ? c->t_grid : 8 * r.block * kU;
+    r.t_grid = (c && c->t_grid) ? c->t_grid : 2 * r.block * kU;
     if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
     if (r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block)) return IRGL_ERR_CONFIG;
     r.grid = c ? c->grid : 0;
@@ -116,12 +149,24 @@ irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
     r.t_bitmap = (c && c->t_bitmap) ? c->t_bitmap : std::max(1u, n / 64u);
     r.trace_len = (c && c->trace) ? c->trace_len : 0u;
     r.trace = (c && c->trace) ? reinterpret_cast<unsigned long long *>(c->trace) : nullptr;
+    // SSSP near/far step: explicit, or derived from the mean weight and mean
+    // degree measured at upload (IRGL_VALIDATE), else plain Bellman-Ford
+    if (c && c->delta) {
+        r.delta = c->delta;
+    } else if (g->weight_sum && g->m > 0) {
+        const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
+        const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
+        const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
+        r.delta = static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
+    } else {
+        r.delta = IRGL_DELTA_NONE;
+    }
     *out = r;
     return IRGL_OK;
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, visited, hub_v, hub_base, total;
+    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, hub_v, hub_base, total;
     uint32_t hub_cap;
 };
 
@@ -131,7 +176,12 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
     L.wl0 = align_up(sizeof(Ctrl));
     L.wl1 = L.wl0 + align_up(static_cast<size_t>(c.cap) * 4);
     L.stamp = L.wl1 + align_up(static_cast<size_t>(c.cap) * 4);
-    L.visited = L.stamp + (kind == IRGL_KIND_SSSP ? align_up(static_cast<size_t>(g->n) * 4) : 0);
+    const size_t nb = align_up(static_cast<size_t>(g->n) * 4);
+    const bool sssp = kind == IRGL_KIND_SSSP;
+    L.far0 = L.stamp + (sssp ? nb : 0);
+    L.far1 = L.far0 + (sssp ? nb : 0);
+    L.far_flag = L.far1 + (sssp ? nb : 0);
+    L.visited = L.far_flag + (sssp ? nb : 0);
     const bool bitmap = kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER;
     L.hub_v = L.visited + (bitmap ? align_up((static_cast<size_t>(g->n) + 31) / 32 * 4) : 0);
     // at most m / t_grid vertices have t_grid or more edges
@@ -213,21 +263,42 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
         if (st) return st;
         uint32_t it = 0;
         int hit_limit = 0;
+        bool transfer = false;  // the next invocation raises the SSSP threshold
+        uint32_t far_n = 0, far_min = IRGL_INF;
         for (;; ++it) {
             if (it >= c.max_iter) {
                 hit_limit = 1;
                 break;
             }
             p.it = it;
-            hipLaunchKernelGGL((level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
-            IRGL_HIP(hipGetLastError());
-            if (p.t_grid > 0) {
-                hipLaunchKernelGGL((hub_level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
+            if (transfer) {
+                const uint32_t lo = std::max(p.thresh, far_min);
+                const uint32_t t_new = lo >= IRGL_INF - p.delta ? IRGL_INF : lo + p.delta;
+                hipLaunchKernelGGL((transfer_kernel<B>), dim3(grid), dim3(B), 0, s, p, far_n, t_new);
                 IRGL_HIP(hipGetLastError());
+                p.thresh = t_new;
+                ++p.far_tr;
+            } else {
+                hipLaunchKernelGGL((level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
+                IRGL_HIP(hipGetLastError());
+                if (p.t_grid > 0) {
+                    hipLaunchKernelGGL((hub_level_kernel<B, Op>), dim3(grid), dim3(B), 0, s, p);
+                    IRGL_HIP(hipGetLastError());
+                }
             }
             IRGL_HIP(hipMemcpyAsync(host, &p.ctrl->cnt[(it + 1) % 3], 4, hipMemcpyDeviceToHost, s));
+            if (kind == IRGL_KIND_SSSP) {
+                IRGL_HIP(hipMemcpyAsync(host + 1, &p.ctrl->far_cnt[p.far_tr % 3], 4, hipMemcpyDeviceToHost, s));
+                IRGL_HIP(hipMemcpyAsync(host + 2, &p.ctrl->far_min[p.far_tr % 3], 4, hipMemcpyDeviceToHost, s));
+            }
             IRGL_HIP(hipStreamSynchronize(s));
-            if (*host == 0) break;
+            transfer = false;
+            if (host[0] == 0) {
+                far_n = kind == IRGL_KIND_SSSP ? std::min(host[1], p.far_cap) : 0u;
+                far_min = kind == IRGL_KIND_SSSP ? host[2] : IRGL_INF;
+                if (far_n == 0) break;
+                transfer = true;
+            }
         }
         hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, p, hit_limit);
         IRGL_HIP(hipGetLastError());
@@ -260,6 +331,10 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     if (st) return st;
     const Layout L = layout(g, kind, c);
     if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    // SSSP safety cap also covers the threshold-raise invocations (at most one
+    // per vertex moved from the far list)
+    if (kind == IRGL_KIND_SSSP && !(cfg && cfg->max_iter))
+        c.max_iter = static_cast<uint32_t>(std::min<uint64_t>(0xFFFFFFF0ull, 4ull * static_cast<uint64_t>(g->n) + 16ull));
     int cur = -1;
     IRGL_HIP(hipGetDevice(&cur));
     if (cur != g->device) IRGL_HIP(hipSetDevice(g->device));
@@ -280,6 +355,15 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.visited = (kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER)
                     ? reinterpret_cast<uint32_t *>(base + L.visited) : nullptr;
     p.t_bitmap = c.t_bitmap;
+    if (kind == IRGL_KIND_SSSP) {
+        p.far0 = reinterpret_cast<int32_t *>(base + L.far0);
+        p.far1 = reinterpret_cast<int32_t *>(base + L.far1);
+        p.far_flag = reinterpret_cast<uint32_t *>(base + L.far_flag);
+        p.far_cap = static_cast<uint32_t>(g->n);
+    }
+    p.delta = c.delta;
+    p.thresh = c.delta;
+    p.far_tr = 0;
     p.t_grid = c.t_grid;
     p.hub_cap = L.hub_cap;
     p.hub_v = reinterpret_cast<int32_t *>(base + L.hub_v);
@@ -299,9 +383,226 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     return st;
 }
 
-__device__ uint32_t g_invalid_flag;
+// ---------------------------------------------------------------------------
+// Batched launch (host side)
+// ---------------------------------------------------------------------------
+constexpr int kBatchAlign = 256;
 
-__global__ void clear_flag_kernel() { g_invalid_flag = 0u; }
+struct BatchLayout {
+    size_t queue, team_task, tasks, stats, scratch, total;
+    size_t team_bytes;
+    size_t off_wl0, off_wl1, off_stamp, off_far0, off_far1, off_far_flag, off_visited, off_hub_v, off_hub_base;
+    uint32_t cap, hub_cap;
+    int teams;
+    int team;  // workgroups per team
+};
+
+struct BatchCfg {
+    int block, team, t_wave, t_block, t_grid, grid;
+    uint32_t delta, watchdog_ms;
+};
+
+irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
+    BatchCfg r;
+    r.block = (c && c->block) ? c->block : 256;
+    if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
+    r.team = (c && c->team) ? c->team : 16;
+    if (r.team < 1) return IRGL_ERR_CONFIG;
+    r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
+    r.t_block = (c && c->t_block) ? c->t_block : r.block;
+    r.t_grid = (c && c->t_grid) ? c->t_grid : 2 * r.block * kU;
+    if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
+    if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
+        return IRGL_ERR_CONFIG;
+    r.delta = c ? c->delta : 0u;
+    r.watchdog_ms = (c && c->watchdog_ms) ? c->watchdog_ms : 20000u;
+    r.grid = c ? c->grid : 0;
+    if (r.grid < 0) return IRGL_ERR_CONFIG;
+    *out = r;
+    return IRGL_OK;
+}
+
+irgl_status check_tasks(const irgl_task *tasks, int32_t ntasks) {
+    if (!tasks || ntasks <= 0) return IRGL_ERR_INVALID_ARGUMENT;
+    for (int32_t i = 0; i < ntasks; ++i) {
+        const irgl_task &t = tasks[i];
+        if (!t.g || !t.out) return IRGL_ERR_INVALID_ARGUMENT;
+        if (t.kind != IRGL_KIND_BFS && t.kind != IRGL_KIND_SSSP) return IRGL_ERR_INVALID_ARGUMENT;
+        if (t.src < 0 || t.src >= t.g->n) return IRGL_ERR_INVALID_ARGUMENT;
+        if (t.kind == IRGL_KIND_SSSP && !t.g->w) return IRGL_ERR_NO_WEIGHTS;
+    }
+    return IRGL_OK;
+}
+
+template <int B>
+irgl_status batch_grid(int dev, int requested, int *grid) {
+    return coresident_grid(batch_kernel<B>, B, dev, requested, grid);
+}
+
+// Team layout for graphs of at most nmax vertices / mmax edges; `records`
+// per-task statistics slots (batch: tasks, server: ring slots).
+irgl_status team_layout(int64_t nmax, int64_t mmax, bool any_sssp, bool any_bfs, int32_t records,
+                        const BatchCfg &c, int dev, BatchLayout *out) {
+    BatchLayout L;
+    nmax = std::max<int64_t>(nmax, 1);
+    int grid = 0;
+    irgl_status st = IRGL_OK;
+    switch (c.block) {
+        case 256: st = batch_grid<256>(dev, c.grid, &grid); break;
+        case 512: st = batch_grid<512>(dev, c.grid, &grid); break;
+        default: st = batch_grid<1024>(dev, c.grid, &grid); break;
+    }
+    if (st) return st;
+    const int team = std::min(c.team, grid);
+    L.team = team;
+    L.teams = grid / team;
+    L.cap = static_cast<uint32_t>(nmax);
+    L.hub_cap = c.t_grid > 0 ? static_cast<uint32_t>(std::min<int64_t>(nmax, mmax / c.t_grid + 1)) : 0u;
+    const size_t nb = align_up(static_cast<size_t>(nmax) * 4);
+    size_t o = align_up(sizeof(Ctrl) + sizeof(TaskDesc));  // control block + claimed descriptor
+    L.off_wl0 = o;  o += nb;
+    L.off_wl1 = o;  o += nb;
+    L.off_stamp = o;  o += any_sssp ? nb : 0;
+    L.off_far0 = o;  o += any_sssp ? nb : 0;
+    L.off_far1 = o;  o += any_sssp ? nb : 0;
+    L.off_far_flag = o;  o += any_sssp ? nb : 0;
+    L.off_visited = o;  o += any_bfs ? align_up((static_cast<size_t>(nmax) + 31) / 32 * 4) : 0;
+    L.off_hub_v = o;  o += align_up(static_cast<size_t>(L.hub_cap) * 4);
+    L.off_hub_base = o;  o += align_up(static_cast<size_t>(L.hub_cap) * 4);
+    L.team_bytes = align_up(o);
+    L.queue = 0;
+    L.team_task = align_up(4);
+    L.tasks = L.team_task + align_up(static_cast<size_t>(L.teams) * 4);
+    L.stats = L.tasks + align_up(static_cast<size_t>(records) * sizeof(TaskDesc));
+    L.scratch = L.stats + align_up(static_cast<size_t>(records) * sizeof(Stats));
+    L.total = L.scratch + L.team_bytes * static_cast<size_t>(L.teams);
+    *out = L;
+    return IRGL_OK;
+}
+
+irgl_status batch_layout(const irgl_task *tasks, int32_t ntasks, const BatchCfg &c, int dev,
+                         BatchLayout *out) {
+    int64_t nmax = 1, mmax = 0;
+    bool any_sssp = false, any_bfs = false;
+    for (int32_t i = 0; i < ntasks; ++i) {
+        nmax = std::max<int64_t>(nmax, tasks[i].g->n);
+        mmax = std::max<int64_t>(mmax, tasks[i].g->m);
+        any_sssp |= tasks[i].kind == IRGL_KIND_SSSP;
+        any_bfs |= tasks[i].kind == IRGL_KIND_BFS;
+    }
+    return team_layout(nmax, mmax, any_sssp, any_bfs, ntasks, c, dev, out);
+}
+
+// Reset every team's barrier words (server launches keep the ring head).
+__global__ void team_reset_kernel(char *scratch, unsigned long long team_bytes, int teams) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < teams) {
+        Ctrl *c = reinterpret_cast<Ctrl *>(scratch + static_cast<unsigned long long>(t) * team_bytes);
+        c->bar_gen = 0;
+        c->bar_top = 0;
+        for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
+        c->fatal = 0;
+        c->error = 0;
+    }
+}
+
+__global__ void zero_word_kernel(uint32_t *w) { *w = 0u; }
+
+// Reset the queue head and every team's barrier words.
+__global__ void batch_init_kernel(uint32_t *queue_head, char *scratch, unsigned long long team_bytes,
+                                  int teams) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *queue_head = 0u;
+    if (t < teams) {
+        Ctrl *c = reinterpret_cast<Ctrl *>(scratch + static_cast<unsigned long long>(t) * team_bytes);
+        c->bar_gen = 0;
+        c->bar_top = 0;
+        for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
+        c->fatal = 0;
+        c->error = 0;
+    }
+}
+
+template <int B>
+irgl_status launch_batch(const BatchParams &bp, int grid, hipStream_t s) {
+    void *args[] = {const_cast<BatchParams *>(&bp)};
+    IRGL_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(batch_kernel<B>), dim3(grid), dim3(B),
+                                        args, 0, s));
+    return IRGL_OK;
+}
+
+uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta);
+
+void fill_desc(TaskDesc &d, const irgl_task &t, Stats *stats, uint32_t delta_override) {
+    d.row_ptr = t.g->row_ptr;
+    d.col = t.g->col;
+    d.w = t.g->w;
+    d.out = t.out;
+    d.parent = t.parent;
+    d.stats = stats;
+    d.n = t.g->n;
+    d.kind = t.kind;
+    d.src = t.src;
+    d.delta = t.kind == IRGL_KIND_SSSP ? task_delta(t.g, delta_override) : IRGL_DELTA_NONE;
+    const uint64_t n = static_cast<uint64_t>(t.g->n);
+    d.max_iter = t.kind == IRGL_KIND_SSSP ? static_cast<uint32_t>(std::min<uint64_t>(0xFFFFFFF0ull, 4 * n + 16))
+                                          : static_cast<uint32_t>(n + 1);
+    d.pad = 0;
+}
+
+void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const BatchCfg &c,
+                       const DeviceInfo &di) {
+    std::memset(&bp, 0, sizeof(bp));
+    bp.tasks = reinterpret_cast<const TaskDesc *>(base + L.tasks);
+    bp.queue_head = reinterpret_cast<uint32_t *>(base + L.queue);
+    bp.team_task = reinterpret_cast<uint32_t *>(base + L.team_task);
+    bp.scratch = base + L.scratch;
+    bp.team_bytes = L.team_bytes;
+    bp.off_wl0 = L.off_wl0;
+    bp.off_wl1 = L.off_wl1;
+    bp.off_stamp = L.off_stamp;
+    bp.off_far0 = L.off_far0;
+    bp.off_far1 = L.off_far1;
+    bp.off_far_flag = L.off_far_flag;
+    bp.off_visited = L.off_visited;
+    bp.off_hub_v = L.off_hub_v;
+    bp.off_hub_base = L.off_hub_base;
+    bp.cap = L.cap;
+    bp.hub_cap = L.hub_cap;
+    bp.team = L.team;
+    bp.t_wave = c.t_wave;
+    bp.t_block = c.t_block;
+    bp.t_grid = c.t_grid;
+    bp.t_bitmap_div = 64;
+    bp.wd_ticks = static_cast<unsigned long long>(c.watchdog_ms) * di.wallclock_khz;
+}
+
+template <int B>
+irgl_status launch_server(const ServerParams &sp, int grid, hipStream_t s) {
+    void *args[] = {const_cast<ServerParams *>(&sp)};
+    IRGL_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(server_kernel<B>), dim3(grid), dim3(B),
+                                        args, 0, s));
+    return IRGL_OK;
+}
+
+uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta) {
+    if (override_delta) return override_delta;
+    if (g->weight_sum && g->m > 0) {
+        const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
+        const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
+        const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
+        return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
+    }
+    return IRGL_DELTA_NONE;
+}
+
+__device__ uint32_t g_invalid_flag;
+__device__ unsigned long long g_weight_sum;
+
+__global__ void clear_flag_kernel() {
+    g_invalid_flag = 0u;
+    g_weight_sum = 0ull;
+}
 
 }  // namespace
 
@@ -360,18 +661,22 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     }
     int dev = 0;
     IRGL_HIP(hipGetDevice(&dev));
+    unsigned long long weight_sum = 0;
     if (csr->flags & IRGL_VALIDATE) {
         hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, 0);
         IRGL_HIP(hipGetLastError());
         uint32_t *flag = nullptr;
+        unsigned long long *wsum = nullptr;
         IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&flag), HIP_SYMBOL(g_invalid_flag)));
+        IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&wsum), HIP_SYMBOL(g_weight_sum)));
         const int grid = std::min<int64_t>(4096, std::max<int64_t>(1, (csr->m + 255) / 256));
         hipLaunchKernelGGL(validate_kernel, dim3(grid), dim3(256), 0, 0, csr->n, csr->m, csr->row_ptr,
-                           csr->col, csr->w, flag);
+                           csr->col, csr->w, flag, wsum);
         IRGL_HIP(hipGetLastError());
         uint32_t bad = 0;
         IRGL_HIP(hipMemcpy(&bad, flag, 4, hipMemcpyDeviceToHost));
         if (bad) return IRGL_ERR_INVALID_GRAPH;
+        IRGL_HIP(hipMemcpy(&weight_sum, wsum, 8, hipMemcpyDeviceToHost));
     }
     irgl_graph_s *g = new (std::nothrow) irgl_graph_s;
     if (!g) return IRGL_ERR_INVALID_ARGUMENT;
@@ -382,6 +687,7 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     g->w = csr->w;
     g->flags = csr->flags;
     g->device = dev;
+    g->weight_sum = csr->w ? weight_sum : 0;
     *out = g;
     return IRGL_OK;
 }
@@ -429,4 +735,346 @@ irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out) {
     return IRGL_OK;
 }
 
+
+irgl_status irgl_control_block_sizes(int32_t *sizes, int32_t cap, int32_t *count) {
+    if (!count || (cap > 0 && !sizes)) return IRGL_ERR_INVALID_ARGUMENT;
+    // T_BFS and T_SSSP: the fixed workgroup sizes each loop body is compiled
+    // for; the batched control kernel holds both bodies, so T_control is
+    // their intersection.
+    const int32_t t_bfs[] = {256, 512, 1024};
+    const int32_t t_sssp[] = {256, 512, 1024};
+    int32_t k = 0;
+    for (int32_t a : t_bfs)
+        for (int32_t b : t_sssp)
+            if (a == b) {
+                if (k < cap) sizes[k] = a;
+                ++k;
+            }
+    *count = k;
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_workspace_bytes(const irgl_task *tasks, int32_t ntasks, const irgl_batch_config *cfg,
+                                       size_t *bytes) {
+    if (!bytes) return IRGL_ERR_INVALID_ARGUMENT;
+    irgl_status st = check_tasks(tasks, ntasks);
+    if (st) return st;
+    BatchCfg c;
+    st = resolve_batch(cfg, &c);
+    if (st) return st;
+    BatchLayout L;
+    st = batch_layout(tasks, ntasks, c, tasks[0].g->device, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_submit(const irgl_task *tasks, int32_t ntasks, void *ws, size_t ws_bytes,
+                              const irgl_batch_config *cfg, void *stream, irgl_batch *out) {
+    if (!out || !ws) return IRGL_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    irgl_status st = check_tasks(tasks, ntasks);
+    if (st) return st;
+    const int dev = tasks[0].g->device;
+    for (int32_t i = 1; i < ntasks; ++i)
+        if (tasks[i].g->device != dev) return IRGL_ERR_INVALID_ARGUMENT;
+    BatchCfg c;
+    st = resolve_batch(cfg, &c);
+    if (st) return st;
+    BatchLayout L;
+    st = batch_layout(tasks, ntasks, c, dev, &L);
+    if (st) return st;
+    if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    DeviceInfo di;
+    st = device_info(dev, &di);
+    if (st) return st;
+    int cur = -1;
+    IRGL_HIP(hipGetDevice(&cur));
+    if (cur != dev) IRGL_HIP(hipSetDevice(dev));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+
+    irgl_batch_s *b = new (std::nothrow) irgl_batch_s;
+    if (!b) return IRGL_ERR_INVALID_ARGUMENT;
+    b->ntasks = ntasks;
+    b->stream = s;
+    b->waited = false;
+    b->host_tasks = nullptr;
+    b->dev_stats = reinterpret_cast<Stats *>(base + L.stats);
+    if (hipHostMalloc(&b->host_tasks, sizeof(TaskDesc) * ntasks, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        if (b->host_tasks) (void)hipHostFree(b->host_tasks);
+        delete b;
+        return hip_fail(hipGetLastError());
+    }
+    // largest first (longest-processing-time order); stats keep task order
+    std::vector<int32_t> order(ntasks);
+    for (int32_t i = 0; i < ntasks; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t bb) {
+        return tasks[a].g->m + tasks[a].g->n > tasks[bb].g->m + tasks[bb].g->n;
+    });
+    TaskDesc *td = static_cast<TaskDesc *>(b->host_tasks);
+    for (int32_t k = 0; k < ntasks; ++k) fill_desc(td[k], tasks[order[k]], b->dev_stats + order[k], c.delta);
+    BatchParams bp;
+    fill_batch_params(bp, L, base, c, di);
+    bp.ntasks = ntasks;
+    const int grid = L.teams * bp.team;
+
+    st = IRGL_OK;
+    if (hipMemcpyAsync(base + L.tasks, b->host_tasks, sizeof(TaskDesc) * ntasks, hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        st = hip_fail(hipGetLastError());
+    if (!st) {
+        hipLaunchKernelGGL(batch_init_kernel, dim3((L.teams + 255) / 256), dim3(256), 0, s, bp.queue_head,
+                           bp.scratch, bp.team_bytes, L.teams);
+        if (hipGetLastError() != hipSuccess) st = hip_fail(hipGetLastError());
+    }
+    if (!st) {
+        switch (c.block) {
+            case 256: st = launch_batch<256>(bp, grid, s); break;
+            case 512: st = launch_batch<512>(bp, grid, s); break;
+            default: st = launch_batch<1024>(bp, grid, s); break;
+        }
+    }
+    if (!st && hipEventRecord(b->done, s) != hipSuccess) st = hip_fail(hipGetLastError());
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (st) {
+        (void)hipStreamSynchronize(s);
+        (void)hipEventDestroy(b->done);
+        (void)hipHostFree(b->host_tasks);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_wait(irgl_batch b, irgl_stats *per_task) {
+    if (!b) return IRGL_ERR_INVALID_ARGUMENT;
+    IRGL_HIP(hipEventSynchronize(b->done));
+    b->waited = true;
+    if (per_task)
+        IRGL_HIP(hipMemcpy(per_task, b->dev_stats, sizeof(Stats) * b->ntasks, hipMemcpyDeviceToHost));
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_free(irgl_batch b) {
+    if (!b) return IRGL_OK;
+    if (!b->waited) (void)hipEventSynchronize(b->done);
+    (void)hipEventDestroy(b->done);
+    (void)hipHostFree(b->host_tasks);
+    delete b;
+    return IRGL_OK;
+}
+
+static irgl_status server_sizes(const irgl_graph *graphs, int32_t ngraphs, int64_t *nmax, int64_t *mmax,
+                                bool *weighted) {
+    if (!graphs || ngraphs <= 0) return IRGL_ERR_INVALID_ARGUMENT;
+    *nmax = 1;
+    *mmax = 0;
+    *weighted = false;
+    for (int32_t i = 0; i < ngraphs; ++i) {
+        if (!graphs[i]) return IRGL_ERR_INVALID_ARGUMENT;
+        *nmax = std::max<int64_t>(*nmax, graphs[i]->n);
+        *mmax = std::max<int64_t>(*mmax, graphs[i]->m);
+        *weighted |= graphs[i]->w != nullptr;
+    }
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_open_bytes(const irgl_graph *graphs, int32_t ngraphs, const irgl_batch_config *cfg,
+                                  int32_t ring_cap, size_t *bytes) {
+    if (!bytes || ring_cap <= 0) return IRGL_ERR_INVALID_ARGUMENT;
+    int64_t nmax, mmax;
+    bool weighted;
+    irgl_status st = server_sizes(graphs, ngraphs, &nmax, &mmax, &weighted);
+    if (st) return st;
+    BatchCfg c;
+    st = resolve_batch(cfg, &c);
+    if (st) return st;
+    BatchLayout L;
+    st = team_layout(nmax, mmax, weighted, true, ring_cap, c, graphs[0]->device, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return IRGL_OK;
+}
+
+irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irgl_batch_config *cfg,
+                            int32_t ring_cap, uint32_t idle_ms, void *ws, size_t ws_bytes, void *stream,
+                            irgl_server *out) {
+    if (!out || !ws || ring_cap <= 0) return IRGL_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int64_t nmax, mmax;
+    bool weighted;
+    irgl_status st = server_sizes(graphs, ngraphs, &nmax, &mmax, &weighted);
+    if (st) return st;
+    BatchCfg c;
+    st = resolve_batch(cfg, &c);
+    if (st) return st;
+    const int dev = graphs[0]->device;
+    BatchLayout L;
+    st = team_layout(nmax, mmax, weighted, true, ring_cap, c, dev, &L);
+    if (st) return st;
+    if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    DeviceInfo di;
+    st = device_info(dev, &di);
+    if (st) return st;
+    irgl_server_s *sv = new (std::nothrow) irgl_server_s;
+    ServerParams *sp = new (std::nothrow) ServerParams;
+    if (!sv || !sp) {
+        delete sv;
+        delete sp;
+        return IRGL_ERR_INVALID_ARGUMENT;
+    }
+    const size_t ring_b = align_up(sizeof(TaskDesc) * ring_cap);
+    const size_t done_b = align_up(4ull * ring_cap);
+    const size_t stats_b = align_up(sizeof(Stats) * ring_cap);
+    const size_t host_b = ring_b + 256 + done_b + stats_b;
+    void *hm = nullptr;
+    if (hipHostMalloc(&hm, host_b, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        delete sv;
+        delete sp;
+        return hip_fail(hipGetLastError());
+    }
+    std::memset(hm, 0, host_b);
+    char *h = static_cast<char *>(hm);
+    char *base = static_cast<char *>(ws);
+    fill_batch_params(sp->bp, L, base, c, di);
+    sp->bp.ntasks = 0;
+    sp->ring = reinterpret_cast<TaskDesc *>(h);
+    sp->tail = reinterpret_cast<uint32_t *>(h + ring_b);
+    sp->stop = reinterpret_cast<uint32_t *>(h + ring_b + 128);
+    sp->done = reinterpret_cast<uint32_t *>(h + ring_b + 256);
+    sp->host_stats = reinterpret_cast<Stats *>(h + ring_b + 256 + done_b);
+    sp->head = reinterpret_cast<uint32_t *>(base + L.queue);
+    sp->ring_cap = static_cast<uint32_t>(ring_cap);
+    sp->idle_ticks = static_cast<unsigned long long>(idle_ms ? idle_ms : 50u) * di.wallclock_khz;
+    sv->device = dev;
+    sv->stream = static_cast<hipStream_t>(stream);
+    sv->launched = false;
+    sv->block = c.block;
+    sv->grid = L.teams * L.team;
+    sv->delta = c.delta;
+    sv->ring_cap = ring_cap;
+    sv->next_ticket = 0;
+    sv->dev_head = sp->head;
+    sv->dev_stats = reinterpret_cast<Stats *>(base + L.stats);
+    sv->sssp_ok = weighted;
+    sv->mmax = mmax;
+    sv->host_mem = hm;
+    sv->params = sp;
+    if (hipEventCreateWithFlags(&sv->ran, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(hm);
+        delete sv;
+        delete sp;
+        return hip_fail(hipGetLastError());
+    }
+    // the ring head starts at 0 and is kept across server launches
+    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, sv->stream, sp->head);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipEventDestroy(sv->ran);
+        (void)hipHostFree(hm);
+        delete sv;
+        delete sp;
+        return hip_fail(hipGetLastError());
+    }
+    *out = sv;
+    return IRGL_OK;
+}
+
+static irgl_status server_launch(irgl_server_s *sv) {
+    ServerParams *sp = static_cast<ServerParams *>(sv->params);
+    hipLaunchKernelGGL(team_reset_kernel, dim3((sv->grid / sp->bp.team + 255) / 256), dim3(256), 0, sv->stream,
+                       sp->bp.scratch, sp->bp.team_bytes, sv->grid / sp->bp.team);
+    IRGL_HIP(hipGetLastError());
+    irgl_status st;
+    switch (sv->block) {
+        case 256: st = launch_server<256>(*sp, sv->grid, sv->stream); break;
+        case 512: st = launch_server<512>(*sp, sv->grid, sv->stream); break;
+        default: st = launch_server<1024>(*sp, sv->grid, sv->stream); break;
+    }
+    if (st) return st;
+    IRGL_HIP(hipEventRecord(sv->ran, sv->stream));
+    sv->launched = true;
+    return IRGL_OK;
+}
+
+// Launch the server kernel if none is running (it ends after idle_ms).
+static irgl_status server_kick(irgl_server_s *sv, bool check_pending) {
+    if (sv->launched) {
+        const hipError_t q = hipEventQuery(sv->ran);
+        if (q == hipErrorNotReady) return IRGL_OK;  // still running: it will see the new tail
+        if (q != hipSuccess) return hip_fail(q);
+    }
+    ServerParams *sp = static_cast<ServerParams *>(sv->params);
+    if (check_pending) {
+        uint32_t head = 0;
+        IRGL_HIP(hipMemcpy(&head, sv->dev_head, 4, hipMemcpyDeviceToHost));
+        const uint32_t tail = __atomic_load_n(sp->tail, __ATOMIC_ACQUIRE);
+        if (head >= tail) return IRGL_OK;
+    }
+    return server_launch(sv);
+}
+
+irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *ticket) {
+    if (!s || !task || !ticket) return IRGL_ERR_INVALID_ARGUMENT;
+    irgl_status st = check_tasks(task, 1);
+    if (st) return st;
+    if (task->g->device != s->device) return IRGL_ERR_INVALID_ARGUMENT;
+    ServerParams *sp = static_cast<ServerParams *>(s->params);
+    if (task->g->n > static_cast<int64_t>(sp->bp.cap) || task->g->m > s->mmax ||
+        (task->kind == IRGL_KIND_SSSP && !s->sssp_ok))
+        return IRGL_ERR_TOO_LARGE;
+    const uint64_t t = s->next_ticket;
+    const uint32_t slot = static_cast<uint32_t>(t % static_cast<uint64_t>(s->ring_cap));
+    if (t >= static_cast<uint64_t>(s->ring_cap)) {
+        const uint64_t prev = t - static_cast<uint64_t>(s->ring_cap);
+        if (__atomic_load_n(&sp->done[slot], __ATOMIC_ACQUIRE) != static_cast<uint32_t>(prev + 1))
+            return IRGL_ERR_BUSY;
+    }
+    if (t + 1 >= 0xFFFFFFFFull) return IRGL_ERR_BUSY;  // 32-bit ring counters exhausted
+    fill_desc(sp->ring[slot], *task, s->dev_stats + slot, s->delta);
+    __atomic_store_n(&sp->done[slot], 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(const_cast<uint32_t *>(sp->tail), static_cast<uint32_t>(t + 1), __ATOMIC_RELEASE);
+    s->next_ticket = t + 1;
+    *ticket = t;
+    int cur = -1;
+    IRGL_HIP(hipGetDevice(&cur));
+    if (cur != s->device) IRGL_HIP(hipSetDevice(s->device));
+    st = server_kick(s, false);
+    if (cur != s->device) (void)hipSetDevice(cur);
+    return st;
+}
+
+irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int32_t *done) {
+    if (!s || !done || ticket >= s->next_ticket) return IRGL_ERR_INVALID_ARGUMENT;
+    ServerParams *sp = static_cast<ServerParams *>(s->params);
+    const uint32_t slot = static_cast<uint32_t>(ticket % static_cast<uint64_t>(s->ring_cap));
+    const uint32_t d = __atomic_load_n(&sp->done[slot], __ATOMIC_ACQUIRE);
+    if (d == static_cast<uint32_t>(ticket + 1)) {
+        if (st) std::memcpy(st, &sp->host_stats[slot], sizeof(irgl_stats));
+        *done = 1;
+        return IRGL_OK;
+    }
+    *done = 0;
+    if (ticket + static_cast<uint64_t>(s->ring_cap) < s->next_ticket) return IRGL_ERR_INVALID_ARGUMENT;
+    int cur = -1;
+    IRGL_HIP(hipGetDevice(&cur));
+    if (cur != s->device) IRGL_HIP(hipSetDevice(s->device));
+    const irgl_status k = server_kick(s, true);
+    if (cur != s->device) (void)hipSetDevice(cur);
+    return k;
+}
+
+irgl_status irgl_batch_close(irgl_server s) {
+    if (!s) return IRGL_OK;
+    ServerParams *sp = static_cast<ServerParams *>(s->params);
+    __atomic_store_n(const_cast<uint32_t *>(sp->stop), 1u, __ATOMIC_RELEASE);
+    if (s->launched) (void)hipEventSynchronize(s->ran);
+    (void)hipEventDestroy(s->ran);
+    (void)hipHostFree(s->host_mem);
+    delete sp;
+    delete s;
+    return IRGL_OK;
+}
 }  // extern "C"

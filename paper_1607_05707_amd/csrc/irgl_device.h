@@ -31,7 +31,11 @@ struct alignas(128) Ctrl {
     uint32_t pad0a;
     // rotating grid-tier counters, packed (deferred vertices << 40 | chunks)
     unsigned long long hub[3];
-    uint32_t pad0[22];
+    // rotating SSSP far-list counters (indexed by threshold raises so far)
+    uint32_t far_cnt[3];
+    // rotating SSSP lower bounds on the distances of far-listed vertices
+    uint32_t far_min[3];
+    uint32_t pad0[16];
     // line 1: barrier generation (the only word waiting workgroups poll)
     uint32_t bar_gen;
     uint32_t pad1[31];
@@ -203,16 +207,26 @@ struct BarrierState {
     unsigned long long wd_ticks;  // watchdog in wall-clock ticks
 };
 
+// The workgroups that cooperate on one query: the whole grid of a
+// single-query launch, or one group of a batched launch.  Grid-stride loops
+// and the barrier use the team, never blockIdx / gridDim directly.
+struct Team {
+    uint32_t id;    // this workgroup's index in the team
+    uint32_t size;  // workgroups in the team
+};
+
+__device__ __forceinline__ Team whole_grid() { return Team{blockIdx.x, gridDim.x}; }
+
 __device__ __forceinline__ bool grid_barrier(Ctrl *ctrl, BarrierState &bs, int *s_flag,
-                                             const volatile int32_t *abort_flag) {
+                                             const volatile int32_t *abort_flag, Team tm) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (abort_flag && blockIdx.x == 0 &&
+        if (abort_flag && tm.id == 0 &&
             __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
             set_error(ctrl, kErrAborted, true);
-        const uint32_t G = gridDim.x;
+        const uint32_t G = tm.size;
         const uint32_t ngroups = G < kBarGroups ? G : kBarGroups;
-        const uint32_t gid = blockIdx.x % ngroups;
+        const uint32_t gid = tm.id % ngroups;
         const uint32_t gsize = G / ngroups + (gid < G % ngroups ? 1u : 0u);
         const uint32_t epoch = ++bs.epoch;
         const unsigned long long old =

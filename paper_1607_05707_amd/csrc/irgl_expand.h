@@ -1,0 +1,323 @@
+// Frontier expansion: the outer ForAll over the incoming worklist with
+// nested edge parallelism for the inner ForAll (workgroup / wavefront /
+// prefix-sum tiers plus the grid tier), the staged cooperative pushes, and
+// the SSSP far -> near transfer.
+#pragma once
+
+#include "irgl_ops.h"
+
+namespace irgl {
+
+// Where one invocation's pushes go.
+struct Sink {
+    uint32_t *cnt_out;
+    int32_t *out;
+    uint32_t cap;
+    Ctrl *ctrl;
+    uint32_t *min_out;  // far list: running lower bound of listed distances
+};
+
+// The wavefront's two staging queues and where they drain to.
+struct Pushers {
+    WaveQueue<kQueueCap> nq;  // outgoing worklist (near)
+    WaveQueue<kQueueCap> fq;  // SSSP far list
+    Sink sk;
+    Sink skf;
+    uint32_t fmin;            // this lane's far-list lower bound since the last drain
+    __device__ __forceinline__ void near(bool p, int item) {
+        nq.push(p, item, sk.cnt_out, sk.out, sk.cap, sk.ctrl);
+    }
+    __device__ __forceinline__ void far(bool p, int item) {
+        fq.push(p, item, skf.cnt_out, skf.out, skf.cap, skf.ctrl);
+    }
+};
+
+// Workgroup-wide drain of both queues (all threads call it).
+template <int B, class Op, class S>
+__device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
+    block_drain<B, kQueueCap>(pu.nq, sm.fill, &sm.base, pu.sk.cnt_out, pu.sk.out, pu.sk.cap, pu.sk.ctrl);
+    if (Op::kFar) {
+        block_drain<B, kQueueCap>(pu.fq, sm.fill, &sm.base, pu.skf.cnt_out, pu.skf.out, pu.skf.cap,
+                                  pu.skf.ctrl);
+        // one atomicMin per workgroup for the far-list lower bound
+        uint32_t m = pu.fmin;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) m = min(m, static_cast<uint32_t>(__shfl_xor(m, d, kWave)));
+        __syncthreads();  // every wave has finished reading sm.fill in block_drain
+        if (lane_id() == 0) sm.fill[threadIdx.x / kWave] = static_cast<int>(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t bm = kInf;
+            for (int k = 0; k < B / kWave; ++k) bm = min(bm, static_cast<uint32_t>(sm.fill[k]));
+            if (bm != kInf) atomicMin(pu.skf.min_out, bm);
+        }
+        __syncthreads();
+        pu.fmin = kInf;
+    }
+}
+
+// Relax U edges of one lane and push the survivors (all 64 lanes call it).
+template <class Op>
+__device__ __forceinline__ void relax_and_push(const Op &op, const int32_t *__restrict__ col,
+                                               const int (&e)[kU], bool (&act)[kU], const int (&sv)[kU],
+                                               const uint32_t (&sval)[kU], Pushers &pu) {
+    int d[kU];
+    bool far[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+        d[k] = act[k] ? col[e[k]] : 0;
+        far[k] = false;
+    }
+    op.relax(e, d, sv, sval, act, far, pu.fmin);
+    if (Op::kPush) {
+#pragma unroll
+        for (int k = 0; k < kU; ++k) pu.near(act[k], d[k]);
+    }
+    if (Op::kFar) {
+#pragma unroll
+        for (int k = 0; k < kU; ++k) pu.far(far[k], d[k]);
+    }
+}
+
+// A group of `width` lanes (lane index `li` in it) strides the range
+// [r0, r1) of vertex sv, U edges per lane per round.  The trip count is
+// uniform across the group.
+template <class Op>
+__device__ __forceinline__ void stride_range(const Op &op, const int32_t *__restrict__ col, int r0,
+                                             int r1, int sv, uint32_t sval, int li, int width,
+                                             Pushers &pu) {
+    int svs[kU];
+    uint32_t svals[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+        svs[k] = sv;
+        svals[k] = sval;
+    }
+    for (int e0 = r0; e0 < r1; e0 += width * kU) {
+        int e[kU];
+        bool act[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            e[k] = e0 + k * width + li;
+            act[k] = e[k] < r1;
+        }
+        relax_and_push(op, col, e, act, svs, svals, pu);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phase A of one invocation: nested-parallel expansion of the incoming
+// worklist.  `in == nullptr` means the identity worklist 0..cnt_in-1.
+// Vertices of out-degree >= t_grid (t_grid > 0) are appended to the
+// grid-tier list (hub_v / hub_base, counted by *hub_ctr) instead of being
+// expanded here.  Every thread of every workgroup must call it (it
+// synchronises the workgroup).
+// ---------------------------------------------------------------------------
+template <int B, class Op>
+__device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t cnt_in, uint32_t n,
+                                       const int32_t *__restrict__ row_ptr,
+                                       const int32_t *__restrict__ col, const Op &op, Smem<B> &sm,
+                                       Pushers &pu, int t_wave,
+                                       int t_block, int t_grid, int32_t *hub_v, uint32_t *hub_base,
+                                       uint32_t hub_cap, unsigned long long *hub_ctr,
+                                       unsigned long long &edges, Team tm) {
+    constexpr int NW = B / kWave;
+    constexpr int kChunk = B * kU;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wid = tid / kWave;
+    const uint32_t stride = tm.size * B;
+
+    for (uint32_t base = tm.id * B; base < cnt_in; base += stride) {
+        const uint32_t i = base + tid;
+        int v = -1, r0 = 0, r1 = 0;
+        uint32_t val = 0;
+        if (i < cnt_in) {
+            v = in ? in[i] : static_cast<int>(i);
+            if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
+                set_error(pu.sk.ctrl, kErrInternal, false);
+                v = -1;
+            } else {
+                val = op.vertex_value(v);
+                if (op.active(val)) {
+                    r0 = row_ptr[v];
+                    r1 = row_ptr[v + 1];
+                }
+            }
+        }
+        int deg = r1 - r0;
+        edges += static_cast<unsigned long long>(deg);
+
+        // Tier 0: defer the largest ranges to the grid-wide phase.  One packed
+        // atomicAdd per wavefront reserves list slots and chunk numbers for all
+        // its deferring lanes, in lane order, so slot order is chunk order.
+        if (t_grid > 0) {
+            const bool defer = deg >= t_grid;
+            const unsigned long long dm = __ballot(defer);
+            if (dm) {
+                const int chunks = defer ? (deg + kChunk - 1) / kChunk : 0;
+                const int cincl = wave_inclusive_scan(chunks);
+                const int ctotal = __shfl(cincl, kWave - 1, kWave);
+                unsigned long long old = 0;
+                if (lane == 0)
+                    old = atomicAdd(hub_ctr, (static_cast<unsigned long long>(__popcll(dm)) << 40) |
+                                                 static_cast<unsigned long long>(ctotal));
+                old = __shfl(old, 0, kWave);
+                if (defer) {
+                    const uint32_t slot = static_cast<uint32_t>(old >> 40) + lane_rank(dm);
+                    if (slot < hub_cap) {
+                        hub_v[slot] = v;
+                        hub_base[slot] = static_cast<uint32_t>(old & ((1ull << 40) - 1)) +
+                                         static_cast<uint32_t>(cincl - chunks);
+                        deg = 0;
+                    }  // else: list full, expanded here (cannot happen: cap >= m / t_grid + 1)
+                }
+            }
+        }
+
+        // Tier 1: the whole workgroup strides one large neighbour range at a time.
+        while (__syncthreads_or(deg >= t_block)) {
+            if (deg >= t_block) sm.owner = tid;
+            __syncthreads();
+            if (sm.owner == tid) {
+                sm.big_r0 = r0;
+                sm.big_r1 = r1;
+                sm.big_v = v;
+                sm.big_val = val;
+                deg = 0;
+            }
+            __syncthreads();
+            stride_range(op, col, sm.big_r0, sm.big_r1, sm.big_v, sm.big_val, tid, B, pu);
+        }
+
+        // Tier 2: one wavefront strides one medium neighbour range at a time.
+        for (;;) {
+            const unsigned long long m = __ballot(deg >= t_wave);
+            if (m == 0ull) break;
+            const int leader = __ffsll(static_cast<long long>(m)) - 1;
+            const int w0 = __shfl(r0, leader, kWave);
+            const int w1 = __shfl(r1, leader, kWave);
+            const int wv = __shfl(v, leader, kWave);
+            const uint32_t wval = __shfl(val, leader, kWave);
+            if (lane == leader) deg = 0;
+            stride_range(op, col, w0, w1, wv, wval, lane, kWave, pu);
+        }
+
+        // Tier 3: concatenate the remaining small ranges of the workgroup with
+        // an exclusive prefix sum and deal edges to consecutive lanes.
+        const int incl = wave_inclusive_scan(deg);
+        if (lane == kWave - 1) sm.wsum[wid] = incl;
+        sm.vtx[tid] = v;
+        sm.vval[tid] = val;
+        __syncthreads();
+        int total = 0, wpre = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int s = sm.wsum[k];
+            wpre += (k < wid) ? s : 0;
+            total += s;
+        }
+        const int excl = wpre + incl - deg;
+        for (int done = 0; done < total; done += kChunk) {
+            const int lo = max(excl, done);
+            const int hi = min(excl + deg, done + kChunk);
+            for (int k = lo; k < hi; ++k) {
+                sm.gather_edge[k - done] = r0 + (k - excl);
+                sm.gather_owner[k - done] = static_cast<uint16_t>(tid);
+            }
+            __syncthreads();
+            int e[kU], sv[kU];
+            uint32_t sval[kU];
+            bool act[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) {
+                const int slot = k * B + tid;
+                act[k] = slot < total - done;
+                const int o = act[k] ? sm.gather_owner[slot] : 0;
+                e[k] = act[k] ? sm.gather_edge[slot] : 0;
+                sv[k] = sm.vtx[o];
+                sval[k] = sm.vval[o];
+            }
+            relax_and_push(op, col, e, act, sv, sval, pu);
+            __syncthreads();
+        }
+    }
+}
+
+// Phase B (grid tier): every workgroup takes an equal contiguous share of
+// the chunks of the deferred vertices (a chunk is B*U edges of one vertex;
+// hub_base[] is ascending because slots and chunk bases come from one
+// packed counter).  Called by all threads of every workgroup.
+template <int B, class Op>
+__device__ __forceinline__ void expand_hubs(uint32_t nhubs, uint32_t nchunks, const int32_t *hub_v,
+                                            const uint32_t *hub_base,
+                                            const int32_t *__restrict__ row_ptr,
+                                            const int32_t *__restrict__ col, const Op &op, Smem<B> &sm,
+                                            Pushers &pu, Team tm) {
+    constexpr int kChunk = B * kU;
+    const unsigned long long G = tm.size;
+    const uint32_t lo = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(tm.id) / G);
+    const uint32_t hi = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(tm.id + 1) / G);
+    if (lo >= hi) return;  // uniform across the workgroup
+    if (threadIdx.x == 0) {
+        // the last deferred vertex whose first chunk is <= lo
+        uint32_t a = 0, b = nhubs;
+        while (b - a > 1) {
+            const uint32_t mid = (a + b) / 2;
+            if (hub_base[mid] <= lo) a = mid;
+            else b = mid;
+        }
+        sm.hub_h = static_cast<int>(a);
+    }
+    __syncthreads();
+    uint32_t h = static_cast<uint32_t>(sm.hub_h);
+    uint32_t c = lo;
+    while (c < hi && h < nhubs) {
+        const int v = hub_v[h];
+        const uint32_t cb = hub_base[h];
+        const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+        const uint32_t nch = static_cast<uint32_t>((r1 - r0 + kChunk - 1) / kChunk);
+        const uint32_t c_end = min(hi, cb + nch);
+        const int e_lo = r0 + static_cast<int>((c - cb) * kChunk);
+        const int e_hi = min(r1, r0 + static_cast<int>((c_end - cb) * kChunk));
+        const uint32_t val = op.vertex_value(v);
+        stride_range(op, col, e_lo, e_hi, v, val, threadIdx.x, B, pu);
+        c = c_end;
+        ++h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SSSP far -> near transfer after the threshold rises from t_old to t_new.
+// A listed vertex whose distance is already below t_old was expanded at that
+// distance by a near invocation (dropped); one below t_new joins the next
+// worklist; the rest stays listed.  Called by all threads of every workgroup.
+// ---------------------------------------------------------------------------
+template <int B>
+__device__ __forceinline__ void far_transfer(const int32_t *far_in, uint32_t far_n, uint32_t n,
+                                             uint32_t t_old, uint32_t t_new, const uint32_t *dist,
+                                             uint32_t *far_flag, Pushers &pu, Team tm) {
+    const uint32_t stride = tm.size * B;
+    for (uint32_t base = tm.id * B; base < far_n; base += stride) {
+        const uint32_t i = base + threadIdx.x;
+        int v = 0;
+        bool to_near = false, keep = false;
+        if (i < far_n) {
+            v = far_in[i];
+            if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt list entry
+                set_error(pu.sk.ctrl, kErrInternal, false);
+                v = 0;
+            } else {
+                const uint32_t dv = dist[v];
+                if (dv < t_new) far_flag[v] = 0u;
+                to_near = dv >= t_old && dv < t_new;
+                keep = dv >= t_new;
+                if (keep) pu.fmin = min(pu.fmin, dv);
+            }
+        }
+        pu.near(to_near, v);
+        pu.far(keep, v);
+    }
+}
+
+}  // namespace irgl

@@ -1,0 +1,202 @@
+// Per-query parameters and the relax operators (BFS check-and-label, SSSP
+// near/far relaxation, SSSP parent pass) of the data-driven hot path.
+#pragma once
+
+#include "irgl_device.h"
+
+namespace irgl {
+
+
+constexpr int kQueueCap = 256;  // LDS staging entries per wavefront
+constexpr int kU = 4;           // edges per lane per round (memory-level parallelism)
+
+// Shared-memory layout of the frontier kernels for workgroup size B.
+template <int B>
+struct Smem {
+    static constexpr int NW = B / kWave;
+    int gather_edge[B * kU];       // edge index of each slot of the current gather window
+    uint16_t gather_owner[B * kU]; // thread whose vertex owns that edge
+    int vtx[B];                    // popped vertex of each thread
+    uint32_t vval[B];              // its per-vertex value (SSSP distance at pop)
+    int wsum[NW];                  // per-wavefront degree sums for the workgroup scan
+    int fill[NW];                  // per-wavefront queue fill at the workgroup drain
+    int queue[NW][kQueueCap];      // worklist (near) staging
+    int queue_far[NW][kQueueCap];  // SSSP far-list staging
+    int owner;                     // workgroup-tier vertex owner
+    int big_r0, big_r1, big_v;
+    uint32_t big_val;
+    uint32_t base;
+    int flag;
+    int hub_h;                     // grid tier: first deferred vertex of this workgroup
+};
+
+struct Params {
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const uint32_t *w;
+    uint32_t *val;        // level (BFS) or dist (SSSP)
+    int32_t *parent;      // optional
+    uint32_t *stamp;      // SSSP push stamps
+    int32_t *wl0;
+    int32_t *wl1;
+    int32_t *hub_v;       // grid tier: deferred vertices of the current invocation
+    uint32_t *hub_base;   // grid tier: first chunk of each deferred vertex
+    uint32_t hub_cap;
+    Ctrl *ctrl;
+    Stats *dstats;        // optional
+    uint32_t cap;         // worklist capacity
+    uint32_t max_iter;
+    int32_t t_wave;
+    int32_t t_block;
+    int32_t t_grid;       // 0 disables the grid tier
+    int32_t src;
+    uint32_t it;          // host-loop mode: the invocation to run
+    unsigned long long wd_ticks;
+    const volatile int32_t *abort_flag;
+    uint32_t *visited;    // BFS visited bitmap, ceil(n / 32) words
+    uint32_t t_bitmap;    // refresh the bitmap when the incoming worklist is this large
+    uint32_t trace_len;
+    unsigned long long *trace;
+    int32_t *far0;        // SSSP far lists (two buffers), n entries each
+    int32_t *far1;
+    uint32_t *far_flag;   // SSSP: 1 while a vertex is on the far list
+    uint32_t far_cap;
+    uint32_t delta;       // SSSP threshold step (INF: plain Bellman-Ford)
+    uint32_t thresh;      // host-loop mode: current threshold
+    uint32_t far_tr;      // host-loop mode: threshold raises so far
+};
+
+// ---------------------------------------------------------------------------
+// Relax operators.  relax(e, d, sv, sval, act) receives U scanned edges
+// e[k] = (sv[k] -> d[k]) of this lane, act[k] marking the live ones, and
+// leaves act[k] true for each destination that must be pushed.
+// ---------------------------------------------------------------------------
+struct BfsOp {
+    static constexpr bool kPush = true;
+    static constexpr bool kFar = false;
+    uint32_t *level;
+    int32_t *parent;
+    const uint32_t *visited;  // bitmap: a set bit means "visited" (never a false positive)
+    uint32_t next;            // label of vertices found in this invocation
+    __device__ __forceinline__ uint32_t vertex_value(int) const { return 0u; }
+    __device__ __forceinline__ bool active(uint32_t) const { return true; }
+    __device__ __forceinline__ void relax(const int (&)[kU], const int (&d)[kU], const int (&sv)[kU],
+                                          const uint32_t (&)[kU], bool (&act)[kU], bool (&)[kU],
+                                          uint32_t &) const {
+        // Cheapest filter first: the n/8-byte bitmap stays resident in L2.
+        // (visited is null when the bitmap is disabled: a uniform branch)
+        if (visited) {
+            uint32_t wd[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) wd[k] = act[k] ? visited[static_cast<uint32_t>(d[k]) >> 5] : 0u;
+#pragma unroll
+            for (int k = 0; k < kU; ++k) act[k] = act[k] && !(wd[k] & (1u << (d[k] & 31)));
+        }
+        // A plain (possibly stale) load of the level filters most of the rest;
+        // stale values can only read INF, and the CAS decides.
+        uint32_t lv[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) lv[k] = act[k] ? level[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && lv[k] == kInf;
+            if (act[k]) act[k] = atomicCAS(&level[d[k]], kInf, next) == kInf;
+        }
+        if (parent) {
+#pragma unroll
+            for (int k = 0; k < kU; ++k)
+                if (act[k]) parent[d[k]] = sv[k];
+        }
+    }
+};
+
+// SSSP relaxation with a near/far split of the worklist (a bucketed,
+// delta-stepping order of the same data-driven loop): an improved vertex
+// whose new distance is below the current threshold goes to the next
+// invocation's worklist ("near", at most once per invocation by the push
+// stamp); otherwise to the far list (at most once while it is listed, by
+// far_flag).  thresh = INF gives plain bulk-synchronous Bellman-Ford.
+struct SsspOp {
+    static constexpr bool kPush = true;
+    static constexpr bool kFar = true;
+    uint32_t *dist;
+    const uint32_t *w;
+    uint32_t *stamp;
+    uint32_t *far_flag;
+    uint32_t thresh;
+    uint32_t it;
+    Ctrl *ctrl;
+    __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
+    __device__ __forceinline__ bool active(uint32_t) const { return true; }
+    __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],
+                                          const uint32_t (&dv)[kU], bool (&act)[kU],
+                                          bool (&far)[kU], uint32_t &fmin) const {
+        uint32_t nd[kU], cur[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) nd[k] = act[k] ? w[e[k]] : 0u;
+        bool ovf = false;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            const uint32_t s = dv[k] + nd[k];
+            const bool bad = act[k] && (s < dv[k] || s == kInf);  // does not fit below INF
+            ovf |= bad;
+            act[k] = act[k] && !bad;
+            nd[k] = s;
+        }
+        if (ovf) set_error(ctrl, kErrOverflow, false);
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? dist[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && nd[k] < cur[k];
+            if (act[k]) act[k] = nd[k] < atomicMin(&dist[d[k]], nd[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            far[k] = act[k] && nd[k] >= thresh;
+            act[k] = act[k] && nd[k] < thresh;
+            if (far[k]) fmin = min(fmin, nd[k]);  // lower bound of the far list
+        }
+        // near: push d at most once per invocation; far: at most once while listed
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? stamp[d[k]] : (far[k] ? far_flag[d[k]] : it);
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            act[k] = act[k] && cur[k] != it;
+            if (act[k]) act[k] = atomicExch(&stamp[d[k]], it) != it;
+            far[k] = far[k] && cur[k] == 0u;
+            if (far[k]) far[k] = atomicExch(&far_flag[d[k]], 1u) == 0u;
+        }
+    }
+};
+
+// Deterministic SSSP parents after convergence: the smallest-id tight
+// predecessor of every reached vertex (unsigned min over -1 = 0xFFFFFFFF).
+struct SsspParentOp {
+    static constexpr bool kPush = false;
+    static constexpr bool kFar = false;
+    const uint32_t *dist;
+    const uint32_t *w;
+    int32_t *parent;
+    int32_t src;
+    __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
+    __device__ __forceinline__ bool active(uint32_t dv) const { return dv != kInf; }
+    __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&sv)[kU],
+                                          const uint32_t (&dv)[kU], bool (&act)[kU], bool (&)[kU],
+                                          uint32_t &) const {
+        uint32_t s[kU], cur[kU];
+#pragma unroll
+        for (int k = 0; k < kU; ++k) s[k] = act[k] ? dv[k] + w[e[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? dist[d[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kU; ++k) {
+            if (act[k] && d[k] != src && s[k] == cur[k] && s[k] >= dv[k])
+                atomicMin(reinterpret_cast<uint32_t *>(&parent[d[k]]), static_cast<uint32_t>(sv[k]));
+            act[k] = false;
+        }
+    }
+};
+
+}  // namespace irgl

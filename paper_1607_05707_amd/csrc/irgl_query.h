@@ -1,0 +1,436 @@
+// Query-level kernels: initialisation, the visited-bitmap refresh, the
+// outlined persistent Iterate loop, the un-outlined per-invocation kernels,
+// the SSSP parent pass and the on-device CSR validation.
+#pragma once
+
+#include "irgl_expand.h"
+
+namespace irgl {
+
+// ---------------------------------------------------------------------------
+// Initialisation: val = INF except val[src] = 0; parent = -1 except
+// parent[src] = src; stamps = INF; far flags = 0; bitmap = {src}; in = [src];
+// counters and stats cleared.
+// ---------------------------------------------------------------------------
+// Per-query fill, grid-strided over the team.
+__device__ __forceinline__ void init_arrays(const Params &p, int with_stamp, Team tm) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    for (uint32_t i = tm.id * blockDim.x + threadIdx.x; i < n; i += tm.size * blockDim.x) {
+        const bool s = static_cast<int>(i) == p.src;
+        p.val[i] = s ? 0u : kInf;
+        if (p.parent) p.parent[i] = s ? p.src : -1;
+        if (with_stamp) {
+            p.stamp[i] = kInf;
+            p.far_flag[i] = 0u;
+        }
+        if (p.visited && (i & 31u) == 0u)
+            p.visited[i >> 5] = (static_cast<uint32_t>(p.src) >> 5 == i >> 5)
+                                    ? (1u << (p.src & 31)) : 0u;
+    }
+}
+
+// Per-query control-block reset (one thread).  Barrier words are reset only
+// by a fresh launch (reset_barrier): a batched team keeps its barrier
+// counters, which only grow, across the queries it runs.
+__device__ __forceinline__ void init_control(const Params &p, bool reset_barrier) {
+        Ctrl *c = p.ctrl;
+        c->cnt[0] = 1;
+        c->cnt[1] = 0;
+        c->cnt[2] = 0;
+        for (int k = 0; k < 3; ++k) {
+            c->hub[k] = 0;
+            c->far_cnt[k] = 0;
+            c->far_min[k] = kInf;
+        }
+        if (reset_barrier) {
+            c->bar_gen = 0;
+            c->bar_top = 0;
+            for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
+        }
+        c->error = 0;
+        c->fatal = 0;
+        c->done = 0;
+        c->iterations = 0;
+        c->max_frontier = 0;
+        c->items = 0;
+        c->edges = 0;
+        p.wl0[0] = p.src;
+}
+
+__global__ void init_kernel(Params p, int with_stamp) {
+    init_arrays(p, with_stamp, whole_grid());
+    if (blockIdx.x == 0 && threadIdx.x == 0) init_control(p, true);
+}
+
+template <class Op>
+__device__ __forceinline__ Op make_op(const Params &p, uint32_t it, uint32_t thresh);
+
+template <>
+__device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh) {
+    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl};
+}
+
+template <>
+__device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it, uint32_t) {
+    return BfsOp{p.val, p.parent, p.visited, it + 1};
+}
+
+// Refresh the BFS visited bitmap from the level array: one ballot per 64
+// consecutive vertices, coalesced reads, one plain word store per 32
+// vertices.  Readers may see old or new words concurrently; both only ever
+// mark visited vertices, so any mix is a valid filter.
+__device__ __forceinline__ void refresh_bitmap(const Params &p, Team tm) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    const uint32_t stride = tm.size * blockDim.x;
+    for (uint32_t base = tm.id * blockDim.x; base < n; base += stride) {
+        const uint32_t v = base + threadIdx.x;
+        const bool vis = v < n && p.val[v] != kInf;
+        const unsigned long long m = __ballot(vis);
+        const int lane = lane_id();
+        const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
+        if (lane == 0 && v0 < n) p.visited[v0 >> 5] = static_cast<uint32_t>(m);
+        if (lane == 32 && v < n) p.visited[v >> 5] = static_cast<uint32_t>(m >> 32);
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void level_prologue(const Params &, uint32_t, Team) {}
+
+template <>
+__device__ __forceinline__ void level_prologue<BfsOp>(const Params &p, uint32_t cnt_in, Team tm) {
+    if (p.visited && cnt_in >= p.t_bitmap) refresh_bitmap(p, tm);
+}
+
+// Write the control block's statistics to the caller's stats block.
+__device__ __forceinline__ void publish_stats(const Params &p) {
+    Ctrl *c = p.ctrl;
+    if (!p.dstats) return;
+    Stats *s = p.dstats;
+    s->status = static_cast<int32_t>(load_agent(&c->error));
+    s->iterations = c->iterations;
+    s->items = c->items;
+    s->edges = __hip_atomic_load(&c->edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s->max_frontier = c->max_frontier;
+    s->grid = c->grid;
+    s->block = c->block;
+    s->reserved = 0;
+}
+
+// Sum a per-thread counter over the workgroup and add it to *dst.
+template <int B>
+__device__ __forceinline__ void add_block_total(unsigned long long x, unsigned long long *dst) {
+    __shared__ unsigned long long s_total;
+    if (threadIdx.x == 0) s_total = 0;
+    __syncthreads();
+    atomicAdd(&s_total, x);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(dst, s_total);
+}
+
+// Trace of invocation `it` (only when a trace buffer is given): edges this
+// workgroup scanned, and the number of vertices deferred to the grid tier.
+__device__ __forceinline__ void trace_level(const Params &p, uint32_t it, unsigned long long edges,
+                                            const unsigned long long *hub_ctr, Team tm) {
+    __shared__ unsigned long long s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    if (edges) atomicAdd(&s_sum, edges);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&p.trace[4 * it + 2], s_sum);
+        if (tm.id == 0) p.trace[4 * it + 3] = hub_ctr[0] >> 40;
+    }
+}
+
+// Grid tier of invocation `it`: read the settled deferred-vertex counter.
+__device__ __forceinline__ void hub_counts(unsigned long long hc, uint32_t hub_cap, uint32_t &nh,
+                                           uint32_t &nchunks) {
+    nh = min(static_cast<uint32_t>(hc >> 40), hub_cap);
+    nchunks = static_cast<uint32_t>(hc & ((1ull << 40) - 1));
+}
+
+__device__ __forceinline__ uint32_t raise_threshold(uint32_t t, uint32_t delta) {
+    return t >= kInf - delta ? kInf : t + delta;
+}
+
+// The far list that pushes go to after `tr` threshold raises.
+__device__ __forceinline__ Sink far_sink(const Params &p, uint32_t tr) {
+    return Sink{&p.ctrl->far_cnt[tr % 3], (tr & 1u) ? p.far1 : p.far0, p.far_cap, p.ctrl,
+                &p.ctrl->far_min[tr % 3]};
+}
+
+// Next threshold: the far list's lower bound plus delta, so that every raise
+// moves at least the closest listed vertex to the worklist.
+__device__ __forceinline__ uint32_t next_threshold(uint32_t thresh, uint32_t far_min, uint32_t delta) {
+    return raise_threshold(max(thresh, far_min), delta);
+}
+
+// ---------------------------------------------------------------------------
+// The outlined Iterate loop, run by one team (the whole grid of a
+// single-query launch, or one group of a batched launch).  An invocation that
+// deferred vertices to the grid tier has two team barriers (after phase A,
+// after phase B); any other has one.  For SSSP an empty worklist with a
+// non-empty far list is followed by a transfer invocation that raises the
+// threshold by delta.  All control decisions read settled counters after a
+// barrier, so they are uniform across the team.
+// ---------------------------------------------------------------------------
+struct LoopResult {
+    uint32_t iterations;
+    unsigned long long items;
+    unsigned long long edges;  // CSR entries this workgroup scanned
+    uint32_t max_frontier;
+};
+
+template <int B, class Op>
+__device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, Team tm, BarrierState &bs) {
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    Ctrl *ctrl = p.ctrl;
+    Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, {}, {}, kInf};
+    LoopResult r{0u, 0ull, 0ull, 0u};
+    const int32_t *in = p.wl0;
+    int32_t *out = p.wl1;
+    uint32_t it = 0;
+    uint32_t tr = 0;                              // threshold raises so far
+    uint32_t thresh = Op::kFar ? p.delta : kInf;  // near/far split point
+    const bool lead = tm.id == 0 && tid == 0;
+
+    for (;; ++it) {
+        uint32_t cnt_in = load_agent(&ctrl->cnt[it % 3]);
+        if (cnt_in > p.cap) cnt_in = p.cap;  // overflowed pushes were dropped (error set)
+        uint32_t far_n = 0;
+        if (cnt_in == 0) {
+            if (!Op::kFar) break;
+            far_n = min(load_agent(&ctrl->far_cnt[tr % 3]), p.far_cap);
+            if (far_n == 0) break;
+        }
+        if (it >= p.max_iter) {
+            if (lead) set_error(ctrl, kErrIterLimit, false);
+            break;
+        }
+        r.items += cnt_in;
+        r.max_frontier = max(r.max_frontier, cnt_in);
+        if (lead) {
+            store_agent(&ctrl->cnt[(it + 2) % 3], 0u);
+            __hip_atomic_store(&ctrl->hub[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cnt_in == 0) {
+                store_agent(&ctrl->far_cnt[(tr + 2) % 3], 0u);
+                store_agent(&ctrl->far_min[(tr + 2) % 3], kInf);
+            }
+            if (4 * it + 3 < p.trace_len) {
+                p.trace[4 * it] = wall_clock64();
+                p.trace[4 * it + 1] = cnt_in;
+                p.trace[4 * it + 2] = 0;
+                p.trace[4 * it + 3] = 0;
+            }
+        }
+        pu.sk = Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
+        unsigned long long *hub_ctr = &ctrl->hub[it % 3];
+        if (cnt_in == 0) {
+            // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1
+            const uint32_t t_new = next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta);
+            pu.skf = far_sink(p, tr + 1);
+            far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), thresh, t_new,
+                            p.val, p.far_flag, pu, tm);
+            drain_all<B, Op>(pu, sm);
+            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            thresh = t_new;
+            ++tr;
+        } else {
+            pu.skf = far_sink(p, tr);
+            const unsigned long long edges_before = r.edges;
+            level_prologue<Op>(p, cnt_in, tm);
+            const Op op = make_op<Op>(p, it, thresh);
+            expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
+                          p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm);
+            drain_all<B, Op>(pu, sm);
+            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            if (p.t_grid > 0) {
+                uint32_t nh, nchunks;
+                hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
+                           nh, nchunks);
+                if (nh > 0) {
+                    expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, pu, tm);
+                    drain_all<B, Op>(pu, sm);
+                    if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+                }
+            }
+            if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
+        }
+        const int32_t *t = in;
+        in = out;
+        out = const_cast<int32_t *>(t);
+    }
+    r.iterations = it;
+    return r;
+}
+
+// Statistics and completion of a query run by a team: the last workgroup of
+// the team to finish publishes the caller's stats block.
+template <int B>
+__device__ __forceinline__ void finish_query(const Params &p, const LoopResult &r, Team tm) {
+    Ctrl *ctrl = p.ctrl;
+    add_block_total<B>(r.edges, &ctrl->edges);
+    if (threadIdx.x == 0) {
+        if (tm.id == 0) {
+            if (4 * r.iterations < p.trace_len) p.trace[4 * r.iterations] = wall_clock64();
+            ctrl->iterations = r.iterations;
+            ctrl->items = r.items;
+            ctrl->max_frontier = r.max_frontier;
+            ctrl->grid = static_cast<int32_t>(tm.size);
+            ctrl->block = B;
+        }
+        const uint32_t prev = __hip_atomic_fetch_add(&ctrl->done, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == tm.size - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            publish_stats(p);
+        }
+    }
+}
+
+// One query per cooperative launch: the whole grid is the team.
+template <int B, class Op>
+__global__ __launch_bounds__(B) void persistent_kernel(Params p) {
+    __shared__ Smem<B> sm;
+    const Team tm = whole_grid();
+    BarrierState bs{0u, p.wd_ticks};
+    const LoopResult r = run_iterate<B, Op>(p, sm, tm, bs);
+    finish_query<B>(p, r, tm);
+}
+
+// ---------------------------------------------------------------------------
+// Un-outlined form: invocation `p.it` is one launch of level_kernel (phase
+// A) and one of hub_level_kernel (phase B, returns at once when nothing was
+// deferred), or one launch of transfer_kernel for an SSSP threshold raise;
+// the host reads the counters back after each invocation and decides what to
+// launch next.  The host keeps the threshold (p.thresh) and the number of
+// raises (p.far_tr).
+// ---------------------------------------------------------------------------
+template <int B, class Op>
+__global__ __launch_bounds__(B) void level_kernel(Params p) {
+    __shared__ Smem<B> sm;
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    Ctrl *ctrl = p.ctrl;
+    const uint32_t it = p.it;
+    unsigned long long edges = 0;
+    const int32_t *in = (it & 1u) ? p.wl1 : p.wl0;
+    int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
+    uint32_t cnt_in = ctrl->cnt[it % 3];
+    if (cnt_in > p.cap) cnt_in = p.cap;
+    Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl, nullptr},
+               far_sink(p, p.far_tr), kInf};
+    if (blockIdx.x == 0 && tid == 0 && 4 * it + 3 < p.trace_len) {
+        p.trace[4 * it] = wall_clock64();
+        p.trace[4 * it + 1] = cnt_in;
+    }
+    level_prologue<Op>(p, cnt_in, whole_grid());
+    const Op op = make_op<Op>(p, it, p.thresh);
+    expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave, p.t_block,
+                  p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges, whole_grid());
+    drain_all<B, Op>(pu, sm);
+    add_block_total<B>(edges, &ctrl->edges);
+    if (tid == 0 && blockIdx.x == 0) {
+        ctrl->cnt[(it + 2) % 3] = 0;
+        ctrl->hub[(it + 2) % 3] = 0;
+        ctrl->iterations = it + 1;
+        ctrl->items += cnt_in;
+        ctrl->max_frontier = max(ctrl->max_frontier, cnt_in);
+        ctrl->grid = static_cast<int32_t>(gridDim.x);
+        ctrl->block = B;
+    }
+}
+
+template <int B, class Op>
+__global__ __launch_bounds__(B) void hub_level_kernel(Params p) {
+    __shared__ Smem<B> sm;
+    const int wid = threadIdx.x / kWave;
+    Ctrl *ctrl = p.ctrl;
+    const uint32_t it = p.it;
+    uint32_t nh, nchunks;
+    hub_counts(ctrl->hub[it % 3], p.hub_cap, nh, nchunks);
+    if (nh == 0) return;  // uniform across the grid
+    int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
+    Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl, nullptr},
+               far_sink(p, p.far_tr), kInf};
+    const Op op = make_op<Op>(p, it, p.thresh);
+    expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, pu, whole_grid());
+    drain_all<B, Op>(pu, sm);
+}
+
+// SSSP threshold raise of the un-outlined form: far list p.far_tr ->
+// next worklist / far list p.far_tr + 1, threshold p.thresh -> p.t_new.
+template <int B>
+__global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, uint32_t t_new) {
+    __shared__ Smem<B> sm;
+    const int wid = threadIdx.x / kWave;
+    Ctrl *ctrl = p.ctrl;
+    const uint32_t it = p.it;
+    const uint32_t tr = p.far_tr;
+    int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
+    Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl, nullptr},
+               far_sink(p, tr + 1), kInf};
+    if (blockIdx.x == 0 && threadIdx.x == 0 && 4 * it + 3 < p.trace_len) {
+        p.trace[4 * it] = wall_clock64();
+        p.trace[4 * it + 1] = 0;
+    }
+    far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), p.thresh, t_new, p.val,
+                    p.far_flag, pu, whole_grid());
+    drain_all<B, SsspOp>(pu, sm);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl->cnt[(it + 2) % 3] = 0;
+        ctrl->hub[(it + 2) % 3] = 0;
+        ctrl->far_cnt[(tr + 2) % 3] = 0;
+        ctrl->far_min[(tr + 2) % 3] = kInf;
+        ctrl->iterations = it + 1;
+    }
+}
+
+// Host-loop epilogue and the iteration-limit check of the un-outlined form.
+__global__ void finish_kernel(Params p, int hit_limit) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t it = p.ctrl->iterations;
+        if (4 * it < p.trace_len) p.trace[4 * it] = wall_clock64();
+        if (hit_limit) set_error(p.ctrl, kErrIterLimit, false);
+        publish_stats(p);
+    }
+}
+
+// SSSP parent pass over the identity worklist of all n vertices (the grid
+// tier is off: ranges of every size are expanded in place).
+template <int B>
+__global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
+    __shared__ Smem<B> sm;
+    const int wid = threadIdx.x / kWave;
+    Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{nullptr, nullptr, 0u, p.ctrl, nullptr},
+               Sink{nullptr, nullptr, 0u, p.ctrl, nullptr}, kInf};
+    unsigned long long edges = 0;
+    const SsspParentOp op{p.val, p.w, p.parent, p.src};
+    expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr, p.col,
+                            op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, edges,
+                            whole_grid());
+}
+
+// On-device CSR validation: row_ptr[0] == 0, monotone, row_ptr[n] == m,
+// col in [0, n), w >= 1.  Sets *bad to 1 on any violation.
+__global__ void validate_kernel(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                                const uint32_t *w, uint32_t *bad, unsigned long long *wsum) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    if (tid == 0 && (row_ptr[0] != 0 || static_cast<int64_t>(row_ptr[n]) != m)) atomicOr(bad, 1u);
+    for (uint32_t v = tid; v < static_cast<uint32_t>(n); v += stride)
+        if (row_ptr[v + 1] < row_ptr[v]) atomicOr(bad, 1u);
+    unsigned long long ws = 0;
+    for (uint64_t e = tid; e < static_cast<uint64_t>(m); e += stride) {
+        const int32_t d = col[e];
+        if (d < 0 || d >= n) atomicOr(bad, 1u);
+        if (w) {
+            if (w[e] == 0u) atomicOr(bad, 1u);
+            ws += w[e];
+        }
+    }
+    if (w && ws) atomicAdd(wsum, ws);
+}
+
+}  // namespace irgl

@@ -45,6 +45,7 @@ IRGL_MODE_HOST_LOOP = 1
 IRGL_WATCHDOG_IMMEDIATE = 0xFFFFFFFF
 IRGL_BITMAP_NEVER = 0xFFFFFFFF
 IRGL_GRID_TIER_OFF = -1
+IRGL_DELTA_NONE = 0xFFFFFFFF
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
@@ -62,7 +63,7 @@ class irgl_config(ctypes.Structure):
                 ("t_grid", ctypes.c_int32), ("grid", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_uint32),
                 ("wl_capacity", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
                 ("abort_flag", ctypes.c_void_p), ("t_bitmap", ctypes.c_uint32),
-                ("trace_len", ctypes.c_uint32), ("trace", ctypes.c_void_p)]
+                ("trace_len", ctypes.c_uint32), ("delta", ctypes.c_uint32), ("trace", ctypes.c_void_p)]
 
 
 class irgl_stats(ctypes.Structure):
@@ -319,3 +320,233 @@ def upload(g, flags: int = IRGL_VALIDATE) -> Graph:
     """Register a graphgen.CSRGraph whose tensors are already on the device."""
     fl = flags | (IRGL_SYMMETRIC if getattr(g, "symmetric", False) else 0)
     return irgl_graph_upload(g.row_ptr, g.col, g.w, fl)
+
+
+# ---------------------------------------------------------------------------
+# Batched queries (irgl_batch_*): many queries in one persistent launch.
+# ---------------------------------------------------------------------------
+
+class irgl_task(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("kind", ctypes.c_int32), ("src", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("parent", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class irgl_batch_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("team", ctypes.c_int32), ("t_wave", ctypes.c_int32),
+                ("t_block", ctypes.c_int32), ("t_grid", ctypes.c_int32), ("delta", ctypes.c_uint32),
+                ("watchdog_ms", ctypes.c_uint32), ("grid", ctypes.c_int32)]
+
+
+_lib.irgl_control_block_sizes.restype = ctypes.c_int32
+_lib.irgl_control_block_sizes.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
+_lib.irgl_batch_workspace_bytes.restype = ctypes.c_int32
+_lib.irgl_batch_workspace_bytes.argtypes = [ctypes.POINTER(irgl_task), ctypes.c_int32,
+                                            ctypes.POINTER(irgl_batch_config), ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_batch_submit.restype = ctypes.c_int32
+_lib.irgl_batch_submit.argtypes = [ctypes.POINTER(irgl_task), ctypes.c_int32, _c, ctypes.c_size_t,
+                                   ctypes.POINTER(irgl_batch_config), _c, ctypes.POINTER(_c)]
+_lib.irgl_batch_wait.restype = ctypes.c_int32
+_lib.irgl_batch_wait.argtypes = [_c, ctypes.POINTER(irgl_stats)]
+_lib.irgl_batch_free.restype = ctypes.c_int32
+_lib.irgl_batch_free.argtypes = [_c]
+
+
+def irgl_control_block_sizes() -> list:
+    """T_control: workgroup sizes both loop bodies support (usable by the batch kernel)."""
+    buf = (ctypes.c_int32 * 8)()
+    cnt = ctypes.c_int32()
+    _check(_lib.irgl_control_block_sizes(buf, 8, ctypes.byref(cnt)), "irgl_control_block_sizes")
+    return [int(buf[i]) for i in range(min(cnt.value, 8))]
+
+
+def make_batch_config(cfg=None) -> Optional[irgl_batch_config]:
+    if cfg is None or isinstance(cfg, irgl_batch_config):
+        return cfg
+    c = irgl_batch_config()
+    for k, v in dict(cfg).items():
+        setattr(c, k, int(v))
+    return c
+
+
+class Task:
+    """One query of a batch: graph, kind, source, device outputs (allocated here
+    when not given)."""
+
+    def __init__(self, g: Graph, kind: int, src: int, out: Optional[torch.Tensor] = None,
+                 parent: Optional[torch.Tensor] = None, tag: int = 0, with_parent: bool = False):
+        dev = g.row_ptr.device
+        self.g = g
+        self.kind = int(kind)
+        self.src = int(src)
+        self.out = out if out is not None else torch.empty(g.n, dtype=torch.int32, device=dev)
+        if parent is None and with_parent:
+            parent = torch.empty(g.n, dtype=torch.int32, device=dev)
+        self.parent = parent
+        self.tag = int(tag)
+        self.stats = None
+
+
+def _task_array(tasks):
+    arr = (irgl_task * len(tasks))()
+    for i, t in enumerate(tasks):
+        arr[i].g = t.g.handle
+        arr[i].kind = t.kind
+        arr[i].src = t.src
+        arr[i].out = _dev_ptr(t.out, "out", _I32, t.g.n)
+        arr[i].parent = _dev_ptr(t.parent, "parent", _I32, t.g.n) if t.parent is not None else None
+        arr[i].tag = t.tag
+    return arr
+
+
+def irgl_batch_workspace_bytes(tasks, cfg=None) -> int:
+    arr = _task_array(tasks)
+    c = make_batch_config(cfg)
+    out = ctypes.c_size_t()
+    _check(_lib.irgl_batch_workspace_bytes(arr, len(tasks), ctypes.byref(c) if c is not None else None,
+                                           ctypes.byref(out)), "irgl_batch_workspace_bytes")
+    return int(out.value)
+
+
+class Batch:
+    def __init__(self, handle, tasks, ws):
+        self.handle = handle
+        self.tasks = tasks
+        self.ws = ws
+
+    def free(self):
+        if self.handle:
+            _lib.irgl_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def irgl_batch_submit(tasks, ws: Optional[torch.Tensor] = None, cfg=None, stream=None) -> Batch:
+    """Launch all tasks in one persistent launch (asynchronous on `stream`)."""
+    if ws is None:
+        ws = torch.empty(irgl_batch_workspace_bytes(tasks, cfg), dtype=torch.uint8,
+                         device=tasks[0].g.row_ptr.device)
+    arr = _task_array(tasks)
+    c = make_batch_config(cfg)
+    h = ctypes.c_void_p()
+    _check(_lib.irgl_batch_submit(arr, len(tasks), _dev_ptr(ws, "ws", (torch.uint8,)), ws.numel(),
+                                  ctypes.byref(c) if c is not None else None, _stream_handle(stream),
+                                  ctypes.byref(h)), "irgl_batch_submit")
+    return Batch(h.value, list(tasks), ws)
+
+
+def irgl_batch_wait(b: Batch) -> list:
+    """Wait for the batch; returns per-task statistics (task order) and sets task.stats."""
+    st = (irgl_stats * len(b.tasks))()
+    _check(_lib.irgl_batch_wait(b.handle, st), "irgl_batch_wait")
+    out = [st[i].as_dict() for i in range(len(b.tasks))]
+    for t, s in zip(b.tasks, out):
+        t.stats = s
+    return out
+
+
+def irgl_batch_free(b: Batch) -> None:
+    b.free()
+
+
+# ---------------------------------------------------------------------------
+# Open batches / serving (irgl_batch_open / _enqueue / _poll / _close).
+# ---------------------------------------------------------------------------
+
+_lib.irgl_batch_open_bytes.restype = ctypes.c_int32
+_lib.irgl_batch_open_bytes.argtypes = [ctypes.POINTER(_c), ctypes.c_int32, ctypes.POINTER(irgl_batch_config),
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_batch_open.restype = ctypes.c_int32
+_lib.irgl_batch_open.argtypes = [ctypes.POINTER(_c), ctypes.c_int32, ctypes.POINTER(irgl_batch_config),
+                                 ctypes.c_int32, ctypes.c_uint32, _c, ctypes.c_size_t, _c, ctypes.POINTER(_c)]
+_lib.irgl_batch_enqueue.restype = ctypes.c_int32
+_lib.irgl_batch_enqueue.argtypes = [_c, ctypes.POINTER(irgl_task), ctypes.POINTER(ctypes.c_uint64)]
+_lib.irgl_batch_poll.restype = ctypes.c_int32
+_lib.irgl_batch_poll.argtypes = [_c, ctypes.c_uint64, ctypes.POINTER(irgl_stats), ctypes.POINTER(ctypes.c_int32)]
+_lib.irgl_batch_close.restype = ctypes.c_int32
+_lib.irgl_batch_close.argtypes = [_c]
+
+
+def _graph_array(graphs):
+    arr = (ctypes.c_void_p * len(graphs))()
+    for i, g in enumerate(graphs):
+        arr[i] = g.handle
+    return arr
+
+
+def irgl_batch_open_bytes(graphs, cfg=None, ring_cap: int = 256) -> int:
+    c = make_batch_config(cfg)
+    out = ctypes.c_size_t()
+    _check(_lib.irgl_batch_open_bytes(_graph_array(graphs), len(graphs),
+                                      ctypes.byref(c) if c is not None else None, int(ring_cap),
+                                      ctypes.byref(out)), "irgl_batch_open_bytes")
+    return int(out.value)
+
+
+class Server:
+    """An open batch: tasks are enqueued while the server kernel runs."""
+
+    def __init__(self, handle, graphs, ws, stream):
+        self.handle = handle
+        self.graphs = list(graphs)
+        self.ws = ws
+        self.stream = stream
+        self.inflight = {}
+
+    def close(self):
+        if self.handle:
+            _lib.irgl_batch_close(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def irgl_batch_open(graphs, cfg=None, ring_cap: int = 256, idle_ms: int = 50, ws=None, stream=None) -> Server:
+    if ws is None:
+        ws = torch.empty(irgl_batch_open_bytes(graphs, cfg, ring_cap), dtype=torch.uint8,
+                         device=graphs[0].row_ptr.device)
+    c = make_batch_config(cfg)
+    h = ctypes.c_void_p()
+    _check(_lib.irgl_batch_open(_graph_array(graphs), len(graphs), ctypes.byref(c) if c is not None else None,
+                                int(ring_cap), int(idle_ms), _dev_ptr(ws, "ws", (torch.uint8,)), ws.numel(),
+                                _stream_handle(stream), ctypes.byref(h)), "irgl_batch_open")
+    return Server(h.value, graphs, ws, stream)
+
+
+def irgl_batch_enqueue(s: Server, task: Task):
+    """Queue a task; returns its ticket, or None when the ring is full (BUSY)."""
+    arr = _task_array([task])
+    t = ctypes.c_uint64()
+    st = _lib.irgl_batch_enqueue(s.handle, arr, ctypes.byref(t))
+    if st == IRGL_ERR_BUSY:
+        return None
+    _check(st, "irgl_batch_enqueue")
+    s.inflight[int(t.value)] = task
+    return int(t.value)
+
+
+def irgl_batch_poll(s: Server, ticket: int):
+    """Statistics dict when the task has finished, else None."""
+    st = irgl_stats()
+    done = ctypes.c_int32()
+    _check(_lib.irgl_batch_poll(s.handle, int(ticket), ctypes.byref(st), ctypes.byref(done)), "irgl_batch_poll")
+    if done.value:
+        task = s.inflight.pop(int(ticket), None)
+        d = st.as_dict()
+        if task is not None:
+            task.stats = d
+        return d
+    return None
+
+
+def irgl_batch_close(s: Server) -> None:
+    s.close()

@@ -88,3 +88,46 @@ def test_no_device_is_reported():
     h = ctypes.c_void_p()
     assert irgl._lib.irgl_graph_upload(ctypes.byref(csr), ctypes.byref(h)) == irgl.IRGL_ERR_NO_DEVICE
     assert h.value is None
+
+
+def test_ctypes_layouts_match_the_header(tmp_path):
+    """Compile a C probe against include/irgl.h and compare sizes/offsets with
+    the binding's ctypes structures."""
+    import subprocess
+    from paper_1607_05707_amd import irgl
+    structs = {"irgl_csr": irgl.irgl_csr, "irgl_config": irgl.irgl_config, "irgl_stats": irgl.irgl_stats,
+               "irgl_task": irgl.irgl_task, "irgl_batch_config": irgl.irgl_batch_config}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "irgl.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for name, cls in structs.items():
+        assert int(got[f"{name} size"]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(cls, field).offset, (name, field)
+
+
+def test_control_block_sizes_is_the_intersection():
+    from paper_1607_05707_amd import irgl
+    assert irgl.irgl_control_block_sizes() == [256, 512, 1024]
+
+
+def test_batch_argument_errors_without_device():
+    from paper_1607_05707_amd import irgl
+    L = irgl._lib
+    out = ctypes.c_size_t()
+    assert L.irgl_batch_workspace_bytes(None, 3, None, ctypes.byref(out)) == irgl.IRGL_ERR_INVALID_ARGUMENT
+    arr = (irgl.irgl_task * 1)()
+    assert L.irgl_batch_workspace_bytes(arr, 1, None, ctypes.byref(out)) == irgl.IRGL_ERR_INVALID_ARGUMENT
+    h = ctypes.c_void_p()
+    assert L.irgl_batch_submit(arr, 0, 0x1000, 100, None, None, ctypes.byref(h)) == irgl.IRGL_ERR_INVALID_ARGUMENT
+    assert L.irgl_batch_wait(None, None) == irgl.IRGL_ERR_INVALID_ARGUMENT
+    assert L.irgl_batch_free(None) == irgl.IRGL_OK

@@ -79,6 +79,18 @@ def test_rmat_tiers(irgl, t_wave, t_block, t_bitmap):
         _check_query(irgl, g, hg, SSSP, src, cfg)
 
 
+@pytest.mark.parametrize("delta", [1, 7, 64, 0xFFFFFFFF])
+def test_sssp_near_far_deltas(irgl, delta):
+    g = _dev(gg.rmat(13, seed=21, weight_seed=22, wmax=255))
+    hg = irgl.upload(g)
+    for src in gg.pick_sources(g, 2, seed=23):
+        for mode in (0, 1):
+            _check_query(irgl, g, hg, SSSP, src, {"delta": delta, "mode": mode, "block": 256})
+    r = _dev(gg.config_road(width=128))
+    hr = irgl.upload(r)
+    _check_query(irgl, r, hr, SSSP, r.sources[1], {"delta": delta})
+
+
 def test_tiny_random_graphs(irgl):
     rng = np.random.default_rng(77)
     for i in range(40):
