@@ -103,7 +103,7 @@ def batched_section(args, dev):
     mcc = []
     for hg, kind, src in tasks:
         _, _, st = irgl.query(hg, 0, src)
-        mcc.append(st["edges"])
+        mcc.append(st["frontier_edges"])
     cfg = autotune.load("batch")
     t_batch = autotune.time_batch(tasks, cfg, reps=2)
     # plain: one launch per query, back to back on one stream
@@ -214,7 +214,7 @@ def main() -> int:
         st = irgl.read_stats(stats)
         if st["status"] != 0:
             raise SystemExit(f"BFS from {s} failed: {irgl.irgl_status_string(st['status'])}")
-        mcc[s] = st["edges"]
+        mcc[s] = st["frontier_edges"]
         reached[s] = st["items"]
         if i < n_check:
             lv = irgl.as_u32_numpy(out).copy()

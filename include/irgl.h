@@ -71,6 +71,10 @@ enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
 #define IRGL_BITMAP_NEVER 0xFFFFFFFFu
 #define IRGL_GRID_TIER_OFF (-1)
 #define IRGL_DELTA_NONE 0xFFFFFFFFu
+#define IRGL_DO_OFF 0xFFFFFFFFu
+#define IRGL_BARRIER_XCD 0u
+#define IRGL_BARRIER_WORKGROUP 1u
+#define IRGL_BARRIER_XCD_INV 2u
 
 /* Launch modes. */
 enum {
@@ -105,12 +109,13 @@ typedef struct irgl_graph_s *irgl_graph;
  * remaining ranges of a workgroup are concatenated by a prefix sum in LDS and
  * dealt to consecutive lanes. */
 typedef struct irgl_config {
-    int32_t block;        /* threads per workgroup: 256, 512 or 1024 (fixed-block kernels) */
+    int32_t block;        /* threads per workgroup: 256 (default), 512 or 1024 */
     int32_t t_wave;       /* wavefront tier threshold, >= 1 (default 64) */
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default = block) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
-                             barrier (default 8 x block); IRGL_GRID_TIER_OFF = never */
+                             barrier (default max(8 x block, t_block));
+                             IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
     int32_t mode;         /* IRGL_MODE_* */
     uint32_t max_iter;    /* safety cap on invocations (default n + 1 for BFS,
@@ -122,22 +127,41 @@ typedef struct irgl_config {
                              once, to exercise the watchdog path */
     const volatile int32_t *abort_flag; /* HOST pinned memory or NULL; a nonzero value
                              makes the running query stop with IRGL_ERR_ABORTED */
-    uint32_t t_bitmap;    /* BFS: incoming-worklist size at which the visited bitmap
-                             (a level-start snapshot used to skip visited
-                             destinations) is refreshed; default n / 64,
-                             IRGL_BITMAP_NEVER disables it */
+    uint32_t t_bitmap;    /* A bitmap of vertices that cannot improve (BFS: visited;
+                             SSSP: settled, i.e. distance below a drained
+                             threshold) lets relaxations skip them with an L2 bit
+                             test.  It is rebuilt by a full scan once this many
+                             items were popped since the last rebuild (BFS default
+                             n^2 / 2m); IRGL_BITMAP_NEVER disables it (the SSSP
+                             default) */
     uint32_t trace_len;   /* entries of `trace` */
+    uint32_t do_alpha;    /* BFS on a symmetric graph (IRGL_SYMMETRIC): switch an
+                             invocation to bottom-up (every unvisited vertex looks
+                             for a neighbour in the frontier, first hit wins) when
+                             the frontier's edges exceed the unexplored edges /
+                             do_alpha; default 14; IRGL_DO_OFF = always top-down */
+    uint32_t do_beta;     /* ... and back to top-down when the frontier holds fewer
+                             than n / do_beta vertices (default 24) */
     uint32_t delta;       /* SSSP: near/far threshold step.  Distances below the
                              threshold are expanded in bulk-synchronous invocations;
                              larger ones wait on a far list until the threshold has
-                             risen past them.  0 = 8 x mean weight / mean degree when
-                             the graph was uploaded with IRGL_VALIDATE, otherwise
+                             risen past them.  0 = the default: when the graph was
+                             uploaded with IRGL_VALIDATE and its mean degree is below
+                             8, 32 x mean weight / mean degree; otherwise
                              IRGL_DELTA_NONE (plain Bellman-Ford order) */
     uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
                              Four words per invocation i at 4i: wall-clock tick at its
                              start, incoming worklist size, edges scanned (persistent
                              mode), vertices deferred to the grid tier; then the end
                              tick at 4 x iterations */
+    uint32_t barrier;     /* grid-barrier coherence scheme: IRGL_BARRIER_XCD (default:
+                             one L2 write-back per XCD per barrier),
+                             IRGL_BARRIER_WORKGROUP (write-back and invalidate per
+                             workgroup) or IRGL_BARRIER_XCD_INV (also one L2
+                             invalidate per XCD).  The XCD schemes fall back to
+                             IRGL_BARRIER_WORKGROUP for a launch whose workgroups are
+                             not dealt round-robin to the XCDs.  Results do not
+                             depend on it. */
 } irgl_config;
 
 /* Per-query statistics, written by the device when the query ends. */
@@ -150,6 +174,9 @@ typedef struct irgl_stats {
     int32_t grid;          /* workgroups used */
     int32_t block;         /* threads per workgroup used */
     uint32_t reserved;
+    uint64_t frontier_edges; /* sum of the out-degrees of every worklist (BFS: the
+                             CSR entries an exact top-down traversal scans, also
+                             when bottom-up invocations scanned fewer) */
 } irgl_stats;
 
 int irgl_version(void);
@@ -231,6 +258,10 @@ typedef struct irgl_batch_config {
     uint32_t delta;    /* SSSP near/far step for every task (0 = per-graph default) */
     uint32_t watchdog_ms;
     int32_t grid;      /* workgroups (0 = co-resident limit); rounded down to whole teams */
+    uint32_t barrier;  /* team-barrier scheme, as irgl_config.barrier */
+    uint32_t gang_edges; /* open batches: a task on a graph with at least this many
+                            edges runs on the whole grid (all teams together, in
+                            ring order) instead of one team (0 = 2^23) */
 } irgl_batch_config;
 
 typedef struct irgl_batch_s *irgl_batch;
@@ -263,10 +294,12 @@ irgl_status irgl_batch_free(irgl_batch b);
  * Open batches (serving): the teams of a persistent server kernel take
  * tasks from a ring in host pinned memory WHILE the kernel runs, so a
  * request that arrives while others are on the GPU starts as soon as a team
- * is free and overlaps them (continuous batching).  The kernel ends a team
- * after `idle_ms` without work (or at close); irgl_batch_enqueue and
- * irgl_batch_poll relaunch it when work is pending.  Calls on one server
- * must come from one host thread.
+ * is free and overlaps them (continuous batching).  A task on a graph with
+ * at least cfg->gang_edges edges is a gang task: when it reaches the head of
+ * the ring, every team joins it after its current task and the whole grid
+ * runs it.  The kernel ends (all teams together) after `idle_ms` without
+ * work or at close; irgl_batch_enqueue and irgl_batch_poll relaunch it when
+ * work is pending.  Calls on one server must come from one host thread.
  * --------------------------------------------------------------------- */
 typedef struct irgl_server_s *irgl_server;
 
@@ -275,19 +308,26 @@ irgl_status irgl_batch_open_bytes(const irgl_graph *graphs, int32_t ngraphs,
                                   const irgl_batch_config *cfg, int32_t ring_cap, size_t *bytes);
 
 /* Create a server (launches nothing yet).  graphs[]: every graph a task may
- * use (scratch is sized for the largest).  ring_cap: descriptors in flight
- * (queued or running) at most.  ws: device workspace of at least
+ * use (each team's scratch is sized for the largest graph below the gang
+ * threshold, one gang region for the largest at or above it).  ring_cap:
+ * descriptors in flight (queued, running, or finished and not yet polled)
+ * at most.  idle_ms: 0 = 50; at most a quarter of the watchdog
+ * (IRGL_ERR_CONFIG otherwise).  ws: device workspace of at least
  * irgl_batch_open_bytes(...).  The server owns small pinned host buffers. */
 irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irgl_batch_config *cfg,
                             int32_t ring_cap, uint32_t idle_ms, void *ws, size_t ws_bytes, void *stream,
                             irgl_server *out);
 
-/* Queue one task; *ticket identifies it.  IRGL_ERR_BUSY when ring_cap tasks
- * are in flight (retry after polling).  Asynchronous. */
+/* Queue one task; *ticket identifies it (tickets count up from 0).  Ticket t
+ * uses ring slot t % ring_cap, which is free once ticket t - ring_cap has been
+ * reported done by irgl_batch_poll; otherwise IRGL_ERR_BUSY (poll, then
+ * retry).  Asynchronous. */
 irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *ticket);
 
 /* *done = 1 and *st = the task's statistics when the task has finished (its
  * outputs are then visible to the host and other streams), else *done = 0.
+ * A ticket stays pollable until its slot is reused; polling it after that,
+ * or polling a ticket never issued, is IRGL_ERR_INVALID_ARGUMENT.
  * Relaunches the server kernel if it has ended with work pending. */
 irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int32_t *done);
 

@@ -43,12 +43,15 @@ struct irgl_server_s {
     uint32_t delta;
     int32_t ring_cap;
     uint64_t next_ticket;
-    uint32_t *dev_head;      // device: claimed descriptors
+    unsigned long long *dev_head;  // device: claimed | gangs << 32 | pending << 63
     Stats *dev_stats;        // device: per ring slot statistics
     bool sssp_ok;            // scratch includes the SSSP arrays
-    int64_t mmax;            // largest graph the scratch was sized for (edges)
+    int64_t small_n, small_m;  // team regions are sized for these (graphs below gang_edges)
+    int64_t gang_n, gang_m;    // the gang region is sized for these
+    uint32_t gang_edges;
     void *host_mem;          // pinned: ring | tail | stop | done[] | stats[]
     void *params;            // ServerParams (host copy reused for launches)
+    uint64_t *acked;         // per ring slot: 1 + the last ticket polled as done
 };
 
 struct irgl_graph_s {
@@ -78,9 +81,28 @@ irgl_status hip_fail(hipError_t e) {
         if (e_ != hipSuccess) return hip_fail(e_);       \
     } while (0)
 
+static_assert(kBarXcd == IRGL_BARRIER_XCD && kBarWorkgroup == IRGL_BARRIER_WORKGROUP &&
+                  kBarXcdInv == IRGL_BARRIER_XCD_INV,
+              "barrier scheme values");
 constexpr size_t kAlign = 256;
-// default SSSP near/far step = kDeltaScale x mean weight / mean degree
-constexpr double kDeltaScale = 8.0;
+
+// Default bitmap refresh point: a refresh scans all n vertices, so it pays
+// once the vertices reached since the previous refresh carry about n/2
+// edges, i.e. after n^2 / (2m) new vertices (at mean degree m/n).
+uint32_t default_t_bitmap(int64_t n, int64_t m) {
+    if (m <= 0) return static_cast<uint32_t>(std::max<int64_t>(1, n));
+    const double t = static_cast<double>(n) * static_cast<double>(n) / (2.0 * static_cast<double>(m));
+    return static_cast<uint32_t>(std::max(1.0, std::min(static_cast<double>(n), t)));
+}
+// Default SSSP near/far step.  On low-degree (high-diameter) graphs plain
+// Bellman-Ford rescans long chains many times, so the step is kDeltaScale x
+// mean weight / mean degree; at mean degree kDeltaMinDegree and above
+// (scale-free, low diameter) the extra invocations cost more than the
+// re-relaxations they save, and the default is plain Bellman-Ford.
+constexpr double kDeltaScale = 32.0;
+constexpr double kDeltaMinDegree = 8.0;
+
+uint32_t default_delta(const irgl_graph_s *g);
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Per-device facts, looked up once.
@@ -123,18 +145,20 @@ struct Cfg {
     uint32_t trace_len;
     unsigned long long *trace;
     uint32_t delta;
+    uint32_t do_alpha, do_beta;  // do_alpha == 0: no bottom-up invocations
+    uint32_t barrier;
 };
 
-irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
+irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
-    r.block = (c && c->block) ? c->block : 512;
+    r.block = (c && c->block) ? c->block : 256;
     if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
     r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
     r.t_block = (c && c->t_block) ? c->t_block : r.block;
     if (r.t_wave < 1 || r.t_block < r.t_wave) return IRGL_ERR_CONFIG;
     // grid tier: vertices with at least this many edges are split over all
     // workgroups (IRGL_GRID_TIER_OFF disables it)
-    r.t_grid = (c && c->t_grid) ? c->t_grid : 2 * r.block * kU;
+    r.t_grid = (c && c->t_grid) ? c->t_grid : std::max(2 * r.block * kU, r.t_block);
     if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
     if (r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block)) return IRGL_ERR_CONFIG;
     r.grid = c ? c->grid : 0;
@@ -146,27 +170,27 @@ irgl_status resolve(const irgl_graph_s *g, const irgl_config *c, Cfg *out) {
     r.cap = (c && c->wl_capacity) ? std::min(c->wl_capacity, n) : n;
     r.watchdog_ms = (c && c->watchdog_ms) ? c->watchdog_ms : 20000u;
     r.abort_flag = c ? c->abort_flag : nullptr;
-    r.t_bitmap = (c && c->t_bitmap) ? c->t_bitmap : std::max(1u, n / 64u);
+    // BFS: visited filter on by default; SSSP: the settled filter is opt-in
+    // (its refreshes rarely repay on the measured graphs)
+    r.t_bitmap = (c && c->t_bitmap) ? c->t_bitmap
+                                    : (kind == IRGL_KIND_SSSP ? IRGL_BITMAP_NEVER : default_t_bitmap(g->n, g->m));
+    // direction optimization needs in-edges = out-edges and the outlined loop
+    const bool sym = (g->flags & IRGL_SYMMETRIC) != 0;
+    r.do_alpha = (c && c->do_alpha) ? c->do_alpha : 14u;
+    r.do_beta = (c && c->do_beta) ? c->do_beta : 24u;
+    if (!sym || r.do_alpha == IRGL_DO_OFF || r.mode != IRGL_MODE_PERSISTENT) r.do_alpha = 0;
     r.trace_len = (c && c->trace) ? c->trace_len : 0u;
     r.trace = (c && c->trace) ? reinterpret_cast<unsigned long long *>(c->trace) : nullptr;
-    // SSSP near/far step: explicit, or derived from the mean weight and mean
-    // degree measured at upload (IRGL_VALIDATE), else plain Bellman-Ford
-    if (c && c->delta) {
-        r.delta = c->delta;
-    } else if (g->weight_sum && g->m > 0) {
-        const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
-        const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
-        const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
-        r.delta = static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
-    } else {
-        r.delta = IRGL_DELTA_NONE;
-    }
+    // SSSP near/far step: explicit, or derived from the graph's shape
+    r.delta = (c && c->delta) ? c->delta : default_delta(g);
+    r.barrier = c ? c->barrier : IRGL_BARRIER_XCD;
+    if (r.barrier > IRGL_BARRIER_XCD_INV) return IRGL_ERR_CONFIG;
     *out = r;
     return IRGL_OK;
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, hub_v, hub_base, total;
+    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, frontier, hub_v, hub_base, total;
     uint32_t hub_cap;
 };
 
@@ -182,8 +206,11 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
     L.far1 = L.far0 + (sssp ? nb : 0);
     L.far_flag = L.far1 + (sssp ? nb : 0);
     L.visited = L.far_flag + (sssp ? nb : 0);
-    const bool bitmap = kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER;
-    L.hub_v = L.visited + (bitmap ? align_up((static_cast<size_t>(g->n) + 31) / 32 * 4) : 0);
+    const size_t bm = align_up((static_cast<size_t>(g->n) + 31) / 32 * 4);
+    const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
+    const bool bitmap = c.t_bitmap != IRGL_BITMAP_NEVER || pull;
+    L.frontier = L.visited + (bitmap ? bm : 0);
+    L.hub_v = L.frontier + (pull ? bm : 0);
     // at most m / t_grid vertices have t_grid or more edges
     L.hub_cap = c.t_grid > 0
                     ? static_cast<uint32_t>(std::min<int64_t>(g->n, g->m / c.t_grid + 1))
@@ -240,6 +267,7 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
                      ? 0ull
                      : static_cast<unsigned long long>(c.watchdog_ms) * di.wallclock_khz;
     p.abort_flag = c.abort_flag;
+    p.barrier = c.barrier;
 
     hipLaunchKernelGGL(init_kernel, dim3(fill_grid(p.n, 256)), dim3(256), 0, s, p,
                        kind == IRGL_KIND_SSSP ? 1 : 0);
@@ -265,12 +293,16 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
         int hit_limit = 0;
         bool transfer = false;  // the next invocation raises the SSSP threshold
         uint32_t far_n = 0, far_min = IRGL_INF;
+        uint64_t items = 1, refreshed = 0;  // popped items so far / at the last bitmap refresh
         for (;; ++it) {
             if (it >= c.max_iter) {
                 hit_limit = 1;
                 break;
             }
             p.it = it;
+            p.refresh = (items - refreshed >= c.t_bitmap && c.t_bitmap != IRGL_BITMAP_NEVER &&
+                         (transfer || kind == IRGL_KIND_BFS)) ? 1u : 0u;
+            if (p.refresh) refreshed = items;
             if (transfer) {
                 const uint32_t lo = std::max(p.thresh, far_min);
                 const uint32_t t_new = lo >= IRGL_INF - p.delta ? IRGL_INF : lo + p.delta;
@@ -293,6 +325,7 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
             }
             IRGL_HIP(hipStreamSynchronize(s));
             transfer = false;
+            items += host[0];
             if (host[0] == 0) {
                 far_n = kind == IRGL_KIND_SSSP ? std::min(host[1], p.far_cap) : 0u;
                 far_min = kind == IRGL_KIND_SSSP ? host[2] : IRGL_INF;
@@ -327,7 +360,7 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     if (src < 0 || src >= g->n) return IRGL_ERR_INVALID_ARGUMENT;
     if (kind == IRGL_KIND_SSSP && !g->w) return IRGL_ERR_NO_WEIGHTS;
     Cfg c;
-    irgl_status st = resolve(g, cfg, &c);
+    irgl_status st = resolve(g, kind, cfg, &c);
     if (st) return st;
     const Layout L = layout(g, kind, c);
     if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
@@ -352,8 +385,13 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.wl0 = reinterpret_cast<int32_t *>(base + L.wl0);
     p.wl1 = reinterpret_cast<int32_t *>(base + L.wl1);
     p.stamp = kind == IRGL_KIND_SSSP ? reinterpret_cast<uint32_t *>(base + L.stamp) : nullptr;
-    p.visited = (kind == IRGL_KIND_BFS && c.t_bitmap != IRGL_BITMAP_NEVER)
-                    ? reinterpret_cast<uint32_t *>(base + L.visited) : nullptr;
+    const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
+    p.visited = (c.t_bitmap != IRGL_BITMAP_NEVER || pull) ? reinterpret_cast<uint32_t *>(base + L.visited)
+                                                           : nullptr;
+    p.frontier = pull ? reinterpret_cast<uint32_t *>(base + L.frontier) : nullptr;
+    p.do_alpha = c.do_alpha;
+    p.do_beta = c.do_beta;
+    p.m = g->m;
     p.t_bitmap = c.t_bitmap;
     if (kind == IRGL_KIND_SSSP) {
         p.far0 = reinterpret_cast<int32_t *>(base + L.far0);
@@ -386,7 +424,6 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
 // ---------------------------------------------------------------------------
 // Batched launch (host side)
 // ---------------------------------------------------------------------------
-constexpr int kBatchAlign = 256;
 
 struct BatchLayout {
     size_t queue, team_task, tasks, stats, scratch, total;
@@ -397,9 +434,14 @@ struct BatchLayout {
     int team;  // workgroups per team
 };
 
+// Default server gang threshold: a graph with this many edges keeps a
+// 16-workgroup team busy ~50x longer than the whole grid does.
+constexpr uint32_t kDefaultGangEdges = 1u << 23;
+
 struct BatchCfg {
     int block, team, t_wave, t_block, t_grid, grid;
-    uint32_t delta, watchdog_ms;
+    uint32_t delta, watchdog_ms, barrier;
+    uint32_t gang_edges;  // server: tasks on graphs with at least this many edges run on the whole grid
 };
 
 irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
@@ -410,7 +452,7 @@ irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
     if (r.team < 1) return IRGL_ERR_CONFIG;
     r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
     r.t_block = (c && c->t_block) ? c->t_block : r.block;
-    r.t_grid = (c && c->t_grid) ? c->t_grid : 2 * r.block * kU;
+    r.t_grid = (c && c->t_grid) ? c->t_grid : std::max(2 * r.block * kU, r.t_block);
     if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
     if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
         return IRGL_ERR_CONFIG;
@@ -418,6 +460,9 @@ irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
     r.watchdog_ms = (c && c->watchdog_ms) ? c->watchdog_ms : 20000u;
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
+    r.barrier = c ? c->barrier : IRGL_BARRIER_XCD;
+    if (r.barrier > IRGL_BARRIER_XCD_INV) return IRGL_ERR_CONFIG;
+    r.gang_edges = (c && c->gang_edges) ? c->gang_edges : kDefaultGangEdges;
     *out = r;
     return IRGL_OK;
 }
@@ -439,6 +484,27 @@ irgl_status batch_grid(int dev, int requested, int *grid) {
     return coresident_grid(batch_kernel<B>, B, dev, requested, grid);
 }
 
+// One team's (or the gang's) scratch region for graphs of at most nmax
+// vertices / mmax edges: control block, claimed descriptor (and gang
+// record), worklists, SSSP arrays, bitmap and grid-tier list.
+void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, BatchLayout *L) {
+    nmax = std::max<int64_t>(nmax, 1);
+    L->cap = static_cast<uint32_t>(nmax);
+    L->hub_cap = t_grid > 0 ? static_cast<uint32_t>(std::min<int64_t>(nmax, mmax / t_grid + 1)) : 0u;
+    const size_t nb = align_up(static_cast<size_t>(nmax) * 4);
+    size_t o = align_up(sizeof(Ctrl) + sizeof(GangInfo));
+    L->off_wl0 = o;  o += nb;
+    L->off_wl1 = o;  o += nb;
+    L->off_stamp = o;  o += any_sssp ? nb : 0;
+    L->off_far0 = o;  o += any_sssp ? nb : 0;
+    L->off_far1 = o;  o += any_sssp ? nb : 0;
+    L->off_far_flag = o;  o += any_sssp ? nb : 0;
+    L->off_visited = o;  o += align_up((static_cast<size_t>(nmax) + 31) / 32 * 4);
+    L->off_hub_v = o;  o += align_up(static_cast<size_t>(L->hub_cap) * 4);
+    L->off_hub_base = o;  o += align_up(static_cast<size_t>(L->hub_cap) * 4);
+    L->team_bytes = align_up(o);
+}
+
 // Team layout for graphs of at most nmax vertices / mmax edges; `records`
 // per-task statistics slots (batch: tasks, server: ring slots).
 irgl_status team_layout(int64_t nmax, int64_t mmax, bool any_sssp, bool any_bfs, int32_t records,
@@ -456,20 +522,7 @@ irgl_status team_layout(int64_t nmax, int64_t mmax, bool any_sssp, bool any_bfs,
     const int team = std::min(c.team, grid);
     L.team = team;
     L.teams = grid / team;
-    L.cap = static_cast<uint32_t>(nmax);
-    L.hub_cap = c.t_grid > 0 ? static_cast<uint32_t>(std::min<int64_t>(nmax, mmax / c.t_grid + 1)) : 0u;
-    const size_t nb = align_up(static_cast<size_t>(nmax) * 4);
-    size_t o = align_up(sizeof(Ctrl) + sizeof(TaskDesc));  // control block + claimed descriptor
-    L.off_wl0 = o;  o += nb;
-    L.off_wl1 = o;  o += nb;
-    L.off_stamp = o;  o += any_sssp ? nb : 0;
-    L.off_far0 = o;  o += any_sssp ? nb : 0;
-    L.off_far1 = o;  o += any_sssp ? nb : 0;
-    L.off_far_flag = o;  o += any_sssp ? nb : 0;
-    L.off_visited = o;  o += any_bfs ? align_up((static_cast<size_t>(nmax) + 31) / 32 * 4) : 0;
-    L.off_hub_v = o;  o += align_up(static_cast<size_t>(L.hub_cap) * 4);
-    L.off_hub_base = o;  o += align_up(static_cast<size_t>(L.hub_cap) * 4);
-    L.team_bytes = align_up(o);
+    region_layout(nmax, mmax, any_sssp, c.t_grid, &L);
     L.queue = 0;
     L.team_task = align_up(4);
     L.tasks = L.team_task + align_up(static_cast<size_t>(L.teams) * 4);
@@ -494,19 +547,26 @@ irgl_status batch_layout(const irgl_task *tasks, int32_t ntasks, const BatchCfg 
 }
 
 // Reset every team's barrier words (server launches keep the ring head).
-__global__ void team_reset_kernel(char *scratch, unsigned long long team_bytes, int teams) {
+__global__ void zero_head_kernel(unsigned long long *w) { *w = 0ull; }
+
+// Before every server launch: team barrier words, the gang control block's
+// barrier words, and the head word's gang count / pending bit (the claimed
+// count is kept).
+__global__ void server_reset_kernel(char *scratch, unsigned long long team_bytes, int teams, Ctrl *gang,
+                                    unsigned long long *head) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < teams) {
         Ctrl *c = reinterpret_cast<Ctrl *>(scratch + static_cast<unsigned long long>(t) * team_bytes);
-        c->bar_gen = 0;
-        c->bar_top = 0;
-        for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
+        reset_barrier_words(c);
         c->fatal = 0;
         c->error = 0;
+    } else if (t == teams) {
+        reset_barrier_words(gang);
+        gang->fatal = 0;
+        gang->error = 0;
+        *head &= 0xFFFFFFFFull;
     }
 }
-
-__global__ void zero_word_kernel(uint32_t *w) { *w = 0u; }
 
 // Reset the queue head and every team's barrier words.
 __global__ void batch_init_kernel(uint32_t *queue_head, char *scratch, unsigned long long team_bytes,
@@ -515,9 +575,7 @@ __global__ void batch_init_kernel(uint32_t *queue_head, char *scratch, unsigned 
     if (t == 0) *queue_head = 0u;
     if (t < teams) {
         Ctrl *c = reinterpret_cast<Ctrl *>(scratch + static_cast<unsigned long long>(t) * team_bytes);
-        c->bar_gen = 0;
-        c->bar_top = 0;
-        for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
+        reset_barrier_words(c);
         c->fatal = 0;
         c->error = 0;
     }
@@ -533,7 +591,9 @@ irgl_status launch_batch(const BatchParams &bp, int grid, hipStream_t s) {
 
 uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta);
 
-void fill_desc(TaskDesc &d, const irgl_task &t, Stats *stats, uint32_t delta_override) {
+void fill_desc(TaskDesc &d, const irgl_task &t, Stats *stats, uint32_t delta_override, bool gang = false) {
+    std::memset(&d, 0, sizeof(d));
+    d.gang = gang ? 1u : 0u;
     d.row_ptr = t.g->row_ptr;
     d.col = t.g->col;
     d.w = t.g->w;
@@ -547,7 +607,7 @@ void fill_desc(TaskDesc &d, const irgl_task &t, Stats *stats, uint32_t delta_ove
     const uint64_t n = static_cast<uint64_t>(t.g->n);
     d.max_iter = t.kind == IRGL_KIND_SSSP ? static_cast<uint32_t>(std::min<uint64_t>(0xFFFFFFF0ull, 4 * n + 16))
                                           : static_cast<uint32_t>(n + 1);
-    d.pad = 0;
+    d.t_bitmap = t.kind == IRGL_KIND_SSSP ? IRGL_BITMAP_NEVER : default_t_bitmap(t.g->n, t.g->m);
 }
 
 void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const BatchCfg &c,
@@ -573,8 +633,8 @@ void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const 
     bp.t_wave = c.t_wave;
     bp.t_block = c.t_block;
     bp.t_grid = c.t_grid;
-    bp.t_bitmap_div = 64;
     bp.wd_ticks = static_cast<unsigned long long>(c.watchdog_ms) * di.wallclock_khz;
+    bp.barrier = c.barrier;
 }
 
 template <int B>
@@ -586,14 +646,17 @@ irgl_status launch_server(const ServerParams &sp, int grid, hipStream_t s) {
 }
 
 uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta) {
-    if (override_delta) return override_delta;
-    if (g->weight_sum && g->m > 0) {
-        const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
-        const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
-        const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
-        return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
-    }
-    return IRGL_DELTA_NONE;
+    return override_delta ? override_delta : default_delta(g);
+}
+
+// The mean weight is known when the upload validated the graph.
+uint32_t default_delta(const irgl_graph_s *g) {
+    if (!g->weight_sum || g->m <= 0 || g->n <= 0) return IRGL_DELTA_NONE;
+    const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
+    const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
+    if (mean_deg >= kDeltaMinDegree) return IRGL_DELTA_NONE;
+    const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
+    return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
 }
 
 __device__ uint32_t g_invalid_flag;
@@ -703,7 +766,7 @@ irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent
     if (!g || !bytes) return IRGL_ERR_INVALID_ARGUMENT;
     if (kind != IRGL_KIND_BFS && kind != IRGL_KIND_SSSP) return IRGL_ERR_INVALID_ARGUMENT;
     Cfg c;
-    irgl_status st = resolve(g, cfg, &c);
+    irgl_status st = resolve(g, kind, cfg, &c);
     if (st) return st;
     *bytes = layout(g, kind, c).total;
     return IRGL_OK;
@@ -732,6 +795,7 @@ irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out) {
     out->grid = c.grid;
     out->block = c.block;
     out->reserved = 0;
+    out->frontier_edges = c.fedges;
     return IRGL_OK;
 }
 
@@ -867,35 +931,59 @@ irgl_status irgl_batch_free(irgl_batch b) {
     return IRGL_OK;
 }
 
-static irgl_status server_sizes(const irgl_graph *graphs, int32_t ngraphs, int64_t *nmax, int64_t *mmax,
-                                bool *weighted) {
+// Server workspace: the teams' regions sized for the graphs below the gang
+// threshold, then one gang region sized for the graphs at or above it.
+struct ServerPlan {
+    BatchLayout L;   // teams (and the common words / per-slot statistics)
+    BatchLayout G;   // gang region offsets; G.team_bytes = its size (0: no gang graph)
+    size_t gang_off;
+    size_t total;
+    int64_t small_n, small_m, gang_n, gang_m;
+    bool weighted;
+};
+
+static irgl_status server_plan(const irgl_graph *graphs, int32_t ngraphs, const BatchCfg &c, int32_t ring_cap,
+                               ServerPlan *out) {
     if (!graphs || ngraphs <= 0) return IRGL_ERR_INVALID_ARGUMENT;
-    *nmax = 1;
-    *mmax = 0;
-    *weighted = false;
+    ServerPlan P;
+    P.small_n = 1;
+    P.small_m = 0;
+    P.gang_n = 0;
+    P.gang_m = 0;
+    P.weighted = false;
     for (int32_t i = 0; i < ngraphs; ++i) {
         if (!graphs[i]) return IRGL_ERR_INVALID_ARGUMENT;
-        *nmax = std::max<int64_t>(*nmax, graphs[i]->n);
-        *mmax = std::max<int64_t>(*mmax, graphs[i]->m);
-        *weighted |= graphs[i]->w != nullptr;
+        if (graphs[i]->device != graphs[0]->device) return IRGL_ERR_INVALID_ARGUMENT;
+        if (graphs[i]->m >= static_cast<int64_t>(c.gang_edges)) {
+            P.gang_n = std::max<int64_t>(P.gang_n, graphs[i]->n);
+            P.gang_m = std::max<int64_t>(P.gang_m, graphs[i]->m);
+        } else {
+            P.small_n = std::max<int64_t>(P.small_n, graphs[i]->n);
+            P.small_m = std::max<int64_t>(P.small_m, graphs[i]->m);
+        }
+        P.weighted |= graphs[i]->w != nullptr;
     }
+    irgl_status st = team_layout(P.small_n, P.small_m, P.weighted, true, ring_cap, c, graphs[0]->device, &P.L);
+    if (st) return st;
+    P.G = P.L;
+    if (P.gang_n > 0) region_layout(P.gang_n, P.gang_m, P.weighted, c.t_grid, &P.G);
+    else region_layout(1, 0, false, 0, &P.G);  // the gang control block is always there (exit gangs)
+    P.gang_off = P.L.total;
+    P.total = P.gang_off + P.G.team_bytes;
+    *out = P;
     return IRGL_OK;
 }
 
 irgl_status irgl_batch_open_bytes(const irgl_graph *graphs, int32_t ngraphs, const irgl_batch_config *cfg,
                                   int32_t ring_cap, size_t *bytes) {
     if (!bytes || ring_cap <= 0) return IRGL_ERR_INVALID_ARGUMENT;
-    int64_t nmax, mmax;
-    bool weighted;
-    irgl_status st = server_sizes(graphs, ngraphs, &nmax, &mmax, &weighted);
-    if (st) return st;
     BatchCfg c;
-    st = resolve_batch(cfg, &c);
+    irgl_status st = resolve_batch(cfg, &c);
     if (st) return st;
-    BatchLayout L;
-    st = team_layout(nmax, mmax, weighted, true, ring_cap, c, graphs[0]->device, &L);
+    ServerPlan P;
+    st = server_plan(graphs, ngraphs, c, ring_cap, &P);
     if (st) return st;
-    *bytes = L.total;
+    *bytes = P.total;
     return IRGL_OK;
 }
 
@@ -904,34 +992,39 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
                             irgl_server *out) {
     if (!out || !ws || ring_cap <= 0) return IRGL_ERR_INVALID_ARGUMENT;
     *out = nullptr;
-    int64_t nmax, mmax;
-    bool weighted;
-    irgl_status st = server_sizes(graphs, ngraphs, &nmax, &mmax, &weighted);
-    if (st) return st;
     BatchCfg c;
-    st = resolve_batch(cfg, &c);
+    irgl_status st = resolve_batch(cfg, &c);
     if (st) return st;
+    ServerPlan P;
+    st = server_plan(graphs, ngraphs, c, ring_cap, &P);
+    if (st) return st;
+    const BatchLayout &L = P.L;
     const int dev = graphs[0]->device;
-    BatchLayout L;
-    st = team_layout(nmax, mmax, weighted, true, ring_cap, c, dev, &L);
-    if (st) return st;
-    if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    if (ws_bytes < P.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    // a team waits at its barrier while its leader polls for work, and team 0
+    // ends an idle launch after idle_ms: keep that well inside the watchdog
+    if (idle_ms == 0) idle_ms = 50u;
+    if (idle_ms > c.watchdog_ms / 4) return IRGL_ERR_CONFIG;
     DeviceInfo di;
     st = device_info(dev, &di);
     if (st) return st;
     irgl_server_s *sv = new (std::nothrow) irgl_server_s;
     ServerParams *sp = new (std::nothrow) ServerParams;
-    if (!sv || !sp) {
+    uint64_t *acked = new (std::nothrow) uint64_t[ring_cap]();
+    if (!sv || !sp || !acked) {
         delete sv;
         delete sp;
+        delete[] acked;
         return IRGL_ERR_INVALID_ARGUMENT;
     }
+    sv->acked = acked;
     const size_t ring_b = align_up(sizeof(TaskDesc) * ring_cap);
     const size_t done_b = align_up(4ull * ring_cap);
     const size_t stats_b = align_up(sizeof(Stats) * ring_cap);
     const size_t host_b = ring_b + 256 + done_b + stats_b;
     void *hm = nullptr;
     if (hipHostMalloc(&hm, host_b, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        delete[] acked;
         delete sv;
         delete sp;
         return hip_fail(hipGetLastError());
@@ -941,14 +1034,29 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     char *base = static_cast<char *>(ws);
     fill_batch_params(sp->bp, L, base, c, di);
     sp->bp.ntasks = 0;
+    sp->gang = sp->bp;
+    sp->gang.scratch = base + P.gang_off;
+    sp->gang.team_bytes = P.G.team_bytes;
+    sp->gang.off_wl0 = P.G.off_wl0;
+    sp->gang.off_wl1 = P.G.off_wl1;
+    sp->gang.off_stamp = P.G.off_stamp;
+    sp->gang.off_far0 = P.G.off_far0;
+    sp->gang.off_far1 = P.G.off_far1;
+    sp->gang.off_far_flag = P.G.off_far_flag;
+    sp->gang.off_visited = P.G.off_visited;
+    sp->gang.off_hub_v = P.G.off_hub_v;
+    sp->gang.off_hub_base = P.G.off_hub_base;
+    sp->gang.cap = P.G.cap;
+    sp->gang.hub_cap = P.G.hub_cap;
+    sp->gang.team = L.teams * L.team;
     sp->ring = reinterpret_cast<TaskDesc *>(h);
     sp->tail = reinterpret_cast<uint32_t *>(h + ring_b);
     sp->stop = reinterpret_cast<uint32_t *>(h + ring_b + 128);
     sp->done = reinterpret_cast<uint32_t *>(h + ring_b + 256);
     sp->host_stats = reinterpret_cast<Stats *>(h + ring_b + 256 + done_b);
-    sp->head = reinterpret_cast<uint32_t *>(base + L.queue);
+    sp->head = reinterpret_cast<unsigned long long *>(base + L.queue);
     sp->ring_cap = static_cast<uint32_t>(ring_cap);
-    sp->idle_ticks = static_cast<unsigned long long>(idle_ms ? idle_ms : 50u) * di.wallclock_khz;
+    sp->idle_ticks = static_cast<unsigned long long>(idle_ms) * di.wallclock_khz;
     sv->device = dev;
     sv->stream = static_cast<hipStream_t>(stream);
     sv->launched = false;
@@ -959,21 +1067,27 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sv->next_ticket = 0;
     sv->dev_head = sp->head;
     sv->dev_stats = reinterpret_cast<Stats *>(base + L.stats);
-    sv->sssp_ok = weighted;
-    sv->mmax = mmax;
+    sv->sssp_ok = P.weighted;
+    sv->small_n = P.small_n;
+    sv->small_m = P.small_m;
+    sv->gang_n = P.gang_n;
+    sv->gang_m = P.gang_m;
+    sv->gang_edges = c.gang_edges;
     sv->host_mem = hm;
     sv->params = sp;
     if (hipEventCreateWithFlags(&sv->ran, hipEventDisableTiming) != hipSuccess) {
         (void)hipHostFree(hm);
+        delete[] acked;
         delete sv;
         delete sp;
         return hip_fail(hipGetLastError());
     }
     // the ring head starts at 0 and is kept across server launches
-    hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(1), 0, sv->stream, sp->head);
+    hipLaunchKernelGGL(zero_head_kernel, dim3(1), dim3(1), 0, sv->stream, sp->head);
     if (hipGetLastError() != hipSuccess) {
         (void)hipEventDestroy(sv->ran);
         (void)hipHostFree(hm);
+        delete[] acked;
         delete sv;
         delete sp;
         return hip_fail(hipGetLastError());
@@ -984,8 +1098,9 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
 
 static irgl_status server_launch(irgl_server_s *sv) {
     ServerParams *sp = static_cast<ServerParams *>(sv->params);
-    hipLaunchKernelGGL(team_reset_kernel, dim3((sv->grid / sp->bp.team + 255) / 256), dim3(256), 0, sv->stream,
-                       sp->bp.scratch, sp->bp.team_bytes, sv->grid / sp->bp.team);
+    hipLaunchKernelGGL(server_reset_kernel, dim3((sv->grid / sp->bp.team + 1 + 255) / 256), dim3(256), 0,
+                       sv->stream, sp->bp.scratch, sp->bp.team_bytes, sv->grid / sp->bp.team,
+                       reinterpret_cast<Ctrl *>(sp->gang.scratch), sp->head);
     IRGL_HIP(hipGetLastError());
     irgl_status st;
     switch (sv->block) {
@@ -1008,10 +1123,10 @@ static irgl_status server_kick(irgl_server_s *sv, bool check_pending) {
     }
     ServerParams *sp = static_cast<ServerParams *>(sv->params);
     if (check_pending) {
-        uint32_t head = 0;
-        IRGL_HIP(hipMemcpy(&head, sv->dev_head, 4, hipMemcpyDeviceToHost));
+        unsigned long long hw = 0;
+        IRGL_HIP(hipMemcpy(&hw, sv->dev_head, 8, hipMemcpyDeviceToHost));
         const uint32_t tail = __atomic_load_n(sp->tail, __ATOMIC_ACQUIRE);
-        if (head >= tail) return IRGL_OK;
+        if (static_cast<uint32_t>(hw) >= tail) return IRGL_OK;
     }
     return server_launch(sv);
 }
@@ -1022,18 +1137,18 @@ irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *t
     if (st) return st;
     if (task->g->device != s->device) return IRGL_ERR_INVALID_ARGUMENT;
     ServerParams *sp = static_cast<ServerParams *>(s->params);
-    if (task->g->n > static_cast<int64_t>(sp->bp.cap) || task->g->m > s->mmax ||
-        (task->kind == IRGL_KIND_SSSP && !s->sssp_ok))
+    const bool gang = task->g->m >= static_cast<int64_t>(s->gang_edges);
+    if (task->kind == IRGL_KIND_SSSP && !s->sssp_ok) return IRGL_ERR_TOO_LARGE;
+    if (gang ? (task->g->n > s->gang_n || task->g->m > s->gang_m)
+             : (task->g->n > s->small_n || task->g->m > s->small_m))
         return IRGL_ERR_TOO_LARGE;
     const uint64_t t = s->next_ticket;
     const uint32_t slot = static_cast<uint32_t>(t % static_cast<uint64_t>(s->ring_cap));
-    if (t >= static_cast<uint64_t>(s->ring_cap)) {
-        const uint64_t prev = t - static_cast<uint64_t>(s->ring_cap);
-        if (__atomic_load_n(&sp->done[slot], __ATOMIC_ACQUIRE) != static_cast<uint32_t>(prev + 1))
-            return IRGL_ERR_BUSY;
-    }
-    if (t + 1 >= 0xFFFFFFFFull) return IRGL_ERR_BUSY;  // 32-bit ring counters exhausted
-    fill_desc(sp->ring[slot], *task, s->dev_stats + slot, s->delta);
+    // a slot is reused only after its previous task was reported done by irgl_batch_poll
+    if (t >= static_cast<uint64_t>(s->ring_cap) && s->acked[slot] != t - static_cast<uint64_t>(s->ring_cap) + 1)
+        return IRGL_ERR_BUSY;
+    if (t >= 0xFFFFFFF0ull) return IRGL_ERR_BUSY;  // 32-bit ring counters exhausted
+    fill_desc(sp->ring[slot], *task, s->dev_stats + slot, s->delta, gang);
     __atomic_store_n(&sp->done[slot], 0u, __ATOMIC_RELAXED);
     __atomic_store_n(const_cast<uint32_t *>(sp->tail), static_cast<uint32_t>(t + 1), __ATOMIC_RELEASE);
     s->next_ticket = t + 1;
@@ -1053,6 +1168,7 @@ irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int3
     const uint32_t d = __atomic_load_n(&sp->done[slot], __ATOMIC_ACQUIRE);
     if (d == static_cast<uint32_t>(ticket + 1)) {
         if (st) std::memcpy(st, &sp->host_stats[slot], sizeof(irgl_stats));
+        s->acked[slot] = ticket + 1;
         *done = 1;
         return IRGL_OK;
     }
@@ -1073,6 +1189,7 @@ irgl_status irgl_batch_close(irgl_server s) {
     if (s->launched) (void)hipEventSynchronize(s->ran);
     (void)hipEventDestroy(s->ran);
     (void)hipHostFree(s->host_mem);
+    delete[] s->acked;
     delete sp;
     delete s;
     return IRGL_OK;

@@ -28,20 +28,9 @@ struct TaskDesc {
     int32_t src;
     uint32_t delta;
     uint32_t max_iter;
+    uint32_t t_bitmap;   // bitmap refresh point (new items since the last refresh)
+    uint32_t gang;       // server: run on the whole grid (all teams together)
     uint32_t pad;
-};
-
-// Per-team scratch, carved from the batch workspace (sizes for the largest
-// task of the batch).
-struct TeamScratch {
-    Ctrl *ctrl;
-    int32_t *wl0, *wl1;
-    uint32_t *stamp;
-    int32_t *far0, *far1;
-    uint32_t *far_flag;
-    uint32_t *visited;
-    int32_t *hub_v;
-    uint32_t *hub_base;
 };
 
 struct BatchParams {
@@ -58,8 +47,8 @@ struct BatchParams {
     uint32_t hub_cap;
     int32_t team;              // workgroups per team
     int32_t t_wave, t_block, t_grid;
-    uint32_t t_bitmap_div;     // refresh the bitmap when frontier >= n / t_bitmap_div
     unsigned long long wd_ticks;
+    uint32_t barrier;  // grid-barrier coherence scheme (kBar*)
 };
 
 __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskDesc &t, char *base) {
@@ -79,8 +68,9 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.far1 = sssp ? reinterpret_cast<int32_t *>(base + bp.off_far1) : nullptr;
     p.far_flag = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_far_flag) : nullptr;
     p.far_cap = static_cast<uint32_t>(t.n);
-    p.visited = sssp ? nullptr : reinterpret_cast<uint32_t *>(base + bp.off_visited);
-    p.t_bitmap = max(1u, static_cast<uint32_t>(t.n) / bp.t_bitmap_div);
+    // SSSP without refreshes would only test a bitmap holding the source
+    p.visited = (sssp && t.t_bitmap == kInf) ? nullptr : reinterpret_cast<uint32_t *>(base + bp.off_visited);
+    p.t_bitmap = t.t_bitmap;
     p.hub_v = reinterpret_cast<int32_t *>(base + bp.off_hub_v);
     p.hub_base = reinterpret_cast<uint32_t *>(base + bp.off_hub_base);
     p.hub_cap = bp.hub_cap;
@@ -93,12 +83,18 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.src = t.src;
     p.it = 0;
     p.wd_ticks = bp.wd_ticks;
+    p.barrier = bp.barrier;
     p.abort_flag = nullptr;
     p.trace_len = 0;
     p.trace = nullptr;
     p.delta = sssp ? t.delta : kInf;
     p.thresh = p.delta;
     p.far_tr = 0;
+    p.refresh = 0;
+    p.frontier = nullptr;  // batched BFS runs top-down
+    p.do_alpha = 0;
+    p.do_beta = 0;
+    p.m = 0;
     return p;
 }
 
@@ -115,6 +111,7 @@ __device__ __forceinline__ void write_task_stats(const Params &p, const LoopResu
     s->grid = static_cast<int32_t>(tm.size);
     s->block = block;
     s->reserved = 0;
+    s->frontier_edges = __hip_atomic_load(&p.ctrl->fedges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Run one task on a team: fill, Iterate loop, optional SSSP parent pass.
@@ -133,6 +130,7 @@ __device__ __forceinline__ bool run_task(const BatchParams &bp, const TaskDesc &
     if (td.kind == 1) r = run_iterate<B, SsspOp>(p, sm, tm, bs);
     else r = run_iterate<B, BfsOp>(p, sm, tm, bs);
     add_block_total<B>(r.edges, &ctrl->edges);
+    add_block_total<B>(r.fedges, &ctrl->fedges);
     // every workgroup's edge count and pushes are in before the leader reads them
     if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) return false;
     if (td.kind == 1 && td.parent) {
@@ -159,7 +157,7 @@ __global__ __launch_bounds__(B) void batch_kernel(BatchParams bp) {
     const Team tm{blockIdx.x % static_cast<uint32_t>(bp.team), static_cast<uint32_t>(bp.team)};
     char *base = bp.scratch + static_cast<unsigned long long>(team_id) * bp.team_bytes;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(base);
-    BarrierState bs{0u, bp.wd_ticks};
+    BarrierState bs = make_barrier_state(bp.wd_ticks, bp.barrier);
     const bool leader = tm.id == 0 && threadIdx.x == 0;
 
     for (;;) {
@@ -182,19 +180,30 @@ __global__ __launch_bounds__(B) void batch_kernel(BatchParams bp) {
 // Server: the same teams, fed from a ring of task descriptors in host pinned
 // memory while the kernel runs (continuous batching).  The host writes a
 // descriptor, then publishes it by raising *tail.  A team leader claims the
-// next published slot with a CAS on the device head counter, copies the
+// next published slot with a CAS on the device head word, copies the
 // descriptor to its team's scratch, and the team barrier hands it to the
 // team.  When the task is done the leader writes its statistics to the host
 // ring, releases the outputs at system scope, and raises the slot's done
-// word.  A leader that finds no work polls with back-off and ends its team
-// when the host raises *stop or after idle_ticks without a task (every wait
-// is bounded).
+// word.
+//
+// Gangs.  A descriptor marked `gang` (a task on a large graph) runs on the
+// WHOLE grid instead, in ring order: its claim sets the pending bit of the
+// head word, every team joins it when it next looks for work (after its
+// current task), and the grid-wide gang barrier starts it.  The head word
+// packs the descriptors claimed (bits 0-31), the gangs started in this
+// launch (bits 32-62) and the pending bit (63); a plain claim needs the
+// pending bit clear, so no team starts another task while a gang gathers.
+// Leaving is a gang too: team 0 posts an exit gang on a host stop request or
+// after idle_ticks without work, and after the gang barrier workgroup 0
+// decides for the whole grid whether to end (stop, or still no work) or go
+// on, so the grid always ends together.  Every wait is bounded (watchdog).
 // ---------------------------------------------------------------------------
 struct ServerParams {
     BatchParams bp;                 // team layout and thresholds (bp.tasks unused)
+    BatchParams gang;               // the gang region's layout (scratch = its base)
     TaskDesc *ring;                 // HOST pinned, ring_cap descriptors
     const uint32_t *tail;           // HOST pinned: descriptors published so far
-    uint32_t *head;                 // device: descriptors claimed so far
+    unsigned long long *head;       // device: claimed | gangs << 32 | pending << 63
     uint32_t *done;                 // HOST pinned: per slot, (ticket + 1) when finished
     Stats *host_stats;              // HOST pinned: per slot statistics
     const uint32_t *stop;           // HOST pinned: stop request
@@ -202,12 +211,53 @@ struct ServerParams {
     unsigned long long idle_ticks;
 };
 
+// What the gang region holds after its control block: the claimed
+// descriptor and what the gang is for.
+struct GangInfo {
+    TaskDesc desc;
+    uint32_t ticket;
+    uint32_t kind;      // kGangTask or kGangExit
+    uint32_t decision;  // exit gang: 1 = end the launch
+    uint32_t pad;
+};
+constexpr uint32_t kGangTask = 1;
+constexpr uint32_t kGangExit = 2;
+constexpr unsigned long long kPending = 1ull << 63;
+
 __device__ __forceinline__ uint32_t load_sys(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ unsigned long long load_sys64(const unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void copy_desc(TaskDesc *dst, const TaskDesc *ring_slot) {
+    static_assert(sizeof(TaskDesc) % 8 == 0, "descriptor copied in 8-byte words");
+    // acquire after the tail was seen, then copy word by word
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(ring_slot);
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(dst);
+    for (unsigned k = 0; k < sizeof(TaskDesc) / 8; ++k) d[k] = load_sys64(src + k);
+}
+
+// Statistics of a finished server task to the host ring, the outputs
+// released at system scope, then the slot's done word (one thread).
+__device__ __forceinline__ void report_task(const ServerParams &sp, const TaskDesc &td, uint32_t ticket, bool ok) {
+    const uint32_t slot = ticket % sp.ring_cap;
+    Stats *hs = &sp.host_stats[slot];
+    const Stats *ds = td.stats;
+    hs->status = ok ? ds->status : static_cast<int32_t>(kErrWatchdog);
+    hs->iterations = ds->iterations;
+    hs->items = ds->items;
+    hs->edges = ds->edges;
+    hs->max_frontier = ds->max_frontier;
+    hs->grid = ds->grid;
+    hs->block = ds->block;
+    hs->reserved = 0;
+    hs->frontier_edges = ds->frontier_edges;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __hip_atomic_store(&sp.done[slot], ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <int B>
@@ -221,62 +271,105 @@ __global__ __launch_bounds__(B) void server_kernel(ServerParams sp) {
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(base);
     // this team's copy of the claimed descriptor (right after the control block)
     TaskDesc *mine = reinterpret_cast<TaskDesc *>(base + sizeof(Ctrl));
-    static_assert(sizeof(TaskDesc) % 8 == 0, "descriptor copied in 8-byte words");
-    BarrierState bs{0u, bp.wd_ticks};
+    BarrierState bs = make_barrier_state(bp.wd_ticks, bp.barrier);
+    // the gang region: whole-grid control block and descriptor
+    char *gbase = sp.gang.scratch;
+    Ctrl *gctrl = reinterpret_cast<Ctrl *>(gbase);
+    GangInfo *gi = reinterpret_cast<GangInfo *>(gbase + sizeof(Ctrl));
+    BarrierState gbs = make_barrier_state(bp.wd_ticks, bp.barrier);
+    const Team grid = whole_grid();
     const bool leader = tm.id == 0 && threadIdx.x == 0;
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    constexpr uint32_t kGang = 0xFFFFFFFEu;
+    constexpr uint32_t kQuit = 0xFFFFFFFFu;
+    uint32_t joined = 0;  // gangs this team has joined (leader's copy)
 
     for (;;) {
         if (leader) {
-            uint32_t claimed = kNone;
+            uint32_t action = kGang;
             const unsigned long long t0 = wall_clock64();
             for (;;) {
-                const uint32_t h = load_agent(sp.head);
-                const uint32_t tl = load_sys(sp.tail);
-                if (h < tl) {
-                    if (atomicCAS(sp.head, h, h + 1) == h) {
-                        claimed = h;
+                const unsigned long long hw = __hip_atomic_load(sp.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t h = static_cast<uint32_t>(hw);
+                const uint32_t seq = static_cast<uint32_t>(hw >> 32) & 0x7FFFFFFFu;
+                if (hw & kPending) {
+                    if (seq > joined) {  // a gang this team has not joined yet
+                        joined = seq;
+                        break;
+                    }
+                } else if (h < load_sys(sp.tail)) {
+                    const TaskDesc *slot = &sp.ring[h % sp.ring_cap];
+                    const bool gang = load_sys(&slot->gang) != 0u;
+                    const unsigned long long nw =
+                        gang ? (kPending | (static_cast<unsigned long long>(seq + 1) << 32) | (h + 1u))
+                             : ((hw & ~0xFFFFFFFFull) | (h + 1u));
+                    if (atomicCAS(sp.head, hw, nw) == hw) {
+                        if (gang) {
+                            copy_desc(&gi->desc, slot);
+                            gi->ticket = h;
+                            gi->kind = kGangTask;
+                            joined = seq + 1;
+                        } else {
+                            copy_desc(mine, slot);
+                            action = h;
+                        }
+                        break;
+                    }
+                    continue;
+                } else if (team_id == 0 && (load_sys(sp.stop) || wall_clock64() - t0 > sp.idle_ticks)) {
+                    const unsigned long long nw = kPending | (static_cast<unsigned long long>(seq + 1) << 32) | h;
+                    if (atomicCAS(sp.head, hw, nw) == hw) {
+                        gi->kind = kGangExit;
+                        joined = seq + 1;
                         break;
                     }
                     continue;
                 }
-                if (load_sys(sp.stop) || wall_clock64() - t0 > sp.idle_ticks) break;
+                // every wait ends: a leader that finds neither work nor a gang
+                // for a whole watchdog period (team 0 gone) ends its team
+                if (wall_clock64() - t0 > bp.wd_ticks) {
+                    action = kQuit;
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(8);
             }
-            if (claimed != kNone) {
-                // descriptor: acquire after the tail was seen, then copy word by word
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-                const unsigned long long *src = reinterpret_cast<const unsigned long long *>(
-                    &sp.ring[claimed % sp.ring_cap]);
-                unsigned long long *dst = reinterpret_cast<unsigned long long *>(mine);
-                for (unsigned k = 0; k < sizeof(TaskDesc) / 8; ++k) dst[k] = load_sys64(src + k);
-            }
-            store_agent(&bp.team_task[team_id], claimed);
+            store_agent(&bp.team_task[team_id], action);
         }
         if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) return;
         if (threadIdx.x == 0) s_ticket = load_agent(&bp.team_task[team_id]);
         __syncthreads();
         const uint32_t ticket = s_ticket;
-        if (ticket == kNone) return;  // uniform across the team
+        if (ticket == kQuit) return;  // uniform across the team
+        if (ticket == kGang) {
+            // every team is here: the gang region's descriptor and kind are visible
+            if (!grid_barrier(gctrl, gbs, &sm.flag, nullptr, grid)) return;
+            if (gi->kind == kGangExit) {
+                if (grid.id == 0 && threadIdx.x == 0) {
+                    const uint32_t h = static_cast<uint32_t>(
+                        __hip_atomic_load(sp.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    gi->decision = (load_sys(sp.stop) || h >= load_sys(sp.tail)) ? 1u : 0u;
+                }
+                if (!grid_barrier(gctrl, gbs, &sm.flag, nullptr, grid)) return;
+                // a later gang rewrites the kind and descriptor, never the decision
+                const bool end = gi->decision != 0u;
+                if (grid.id == 0 && threadIdx.x == 0) atomicAnd(sp.head, ~kPending);
+                if (end) return;
+                continue;
+            }
+            const TaskDesc td = gi->desc;
+            const uint32_t gticket = gi->ticket;
+            LoopResult r;
+            const bool ok = run_task<B>(sp.gang, td, gbase, grid, gbs, sm, r);
+            if (grid.id == 0 && threadIdx.x == 0) {
+                report_task(sp, td, gticket, ok);
+                atomicAnd(sp.head, ~kPending);
+            }
+            if (!ok) return;
+            continue;
+        }
         const TaskDesc td = *mine;
         LoopResult r;
         const bool ok = run_task<B>(bp, td, base, tm, bs, sm, r);
-        if (leader) {
-            // statistics to the host ring, outputs released at system scope, then the done word
-            const uint32_t slot = ticket % sp.ring_cap;
-            Stats *hs = &sp.host_stats[slot];
-            const Stats *ds = td.stats;
-            hs->status = ok ? ds->status : static_cast<int32_t>(kErrWatchdog);
-            hs->iterations = ds->iterations;
-            hs->items = ds->items;
-            hs->edges = ds->edges;
-            hs->max_frontier = ds->max_frontier;
-            hs->grid = ds->grid;
-            hs->block = ds->block;
-            hs->reserved = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-            __hip_atomic_store(&sp.done[slot], ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        if (leader) report_task(sp, td, ticket, ok);
         if (!ok) return;
     }
 }

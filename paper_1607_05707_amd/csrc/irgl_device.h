@@ -35,7 +35,9 @@ struct alignas(128) Ctrl {
     uint32_t far_cnt[3];
     // rotating SSSP lower bounds on the distances of far-listed vertices
     uint32_t far_min[3];
-    uint32_t pad0[16];
+    // rotating BFS sums of out-degrees of the next frontier (direction choice)
+    unsigned long long mf[3];
+    uint32_t pad0[10];
     // line 1: barrier generation (the only word waiting workgroups poll)
     uint32_t bar_gen;
     uint32_t pad1[31];
@@ -45,14 +47,16 @@ struct alignas(128) Ctrl {
     // lines 3..10: per-group barrier arrivals
     struct alignas(128) Group {
         unsigned long long count;
-        uint32_t pad[30];
+        uint32_t gen;  // kBarXcdInv: the group's L2 is clean up to this generation
+        uint32_t pad[29];
     } bar_grp[kBarGroups];
     // line 11: errors.  `error` keeps the first code; `fatal` makes waiting
     // workgroups leave the barrier (watchdog, abort).
     uint32_t error;
     uint32_t fatal;
     uint32_t done;  // workgroups that have left the kernel
-    uint32_t pad3[29];
+    uint32_t xmap_bad;  // a workgroup of this launch is not on XCD (id mod 8)
+    uint32_t pad3[28];
     // line 12: statistics
     uint32_t iterations;
     uint32_t max_frontier;
@@ -60,7 +64,8 @@ struct alignas(128) Ctrl {
     unsigned long long edges;
     int32_t grid;
     int32_t block;
-    uint32_t pad4[24];
+    unsigned long long fedges;  // sum of out-degrees of every frontier
+    uint32_t pad4[22];
 };
 static_assert(sizeof(Ctrl) == 13 * 128, "control block layout");
 
@@ -74,6 +79,7 @@ struct Stats {
     int32_t grid;
     int32_t block;
     uint32_t reserved;
+    unsigned long long frontier_edges;
 };
 
 __device__ __forceinline__ void set_error(Ctrl *c, uint32_t code, bool fatal) {
@@ -187,25 +193,70 @@ __device__ __forceinline__ void block_drain(WaveQueue<QCAP> &wq, int *s_fill, ui
 // once, which the cooperative launch guarantees (or refuses to launch).
 //
 // Two-level arrival tree.  Workgroup b arrives on the counter of group
-// b mod 8 (workgroups are dealt round-robin to the eight XCDs, so a group is
-// normally one XCD's workgroups); the last arrival of a group arrives on the
-// top counter; the last top arrival publishes the new generation.  Counters
-// only grow during a query, so "last" is recognised from the value the
-// fetch_add returns and nothing is ever reset.  Each arrival is an acq_rel
-// RMW, so the publishing store happens after every workgroup's writes, and
-// waiters only read the generation word, which lives on a line of its own.
+// b mod 8; the last arrival of a group arrives on the top counter; the last
+// top arrival publishes the new generation.  Counters only grow during a
+// launch, so "last" is recognised from the value the fetch_add returns and
+// nothing is reset.  Waiters poll only the generation word (a line of its
+// own) with s_sleep back-off and relaxed loads.
 //
-// Waiting polls with s_sleep back-off and relaxed loads, then takes one
-// acquire fence.  It gives up when `fatal` is raised or its own wall-clock
-// deadline passes (raising `fatal` itself), so every wait ends.  Workgroup 0
-// reads the optional host abort flag before it arrives; the barrier cannot
+// Coherence.  Each XCD has a private L2, so data written before the barrier
+// must be written back from the writer's L2 and stale lines dropped from the
+// reader's caches.  Three schemes:
+//   kBarWorkgroup: every arrival is an agent-scope acq_rel RMW (an L2
+//     write-back and invalidate per workgroup), then an acquire on exit.
+//   kBarXcd: the hardware deals workgroups round-robin to the XCDs, so group
+//     b mod 8 is exactly one XCD's workgroups and they share one L2.  A
+//     workgroup's stores have reached that L2 when it arrives (its
+//     __syncthreads waits for them), so ONE write-back by the group's last
+//     arrival covers the whole group; every workgroup still takes an acquire
+//     (L1 + L2 invalidate) on exit.
+//   kBarXcdInv: as kBarXcd, and the group's last arrival also does the one
+//     L2 invalidate for its XCD, then releases its group through a group
+//     word; the others drop only their CU's L1.
+// The XCD schemes are correct only under round-robin dispatch, which every
+// workgroup checks against the hardware XCC id before its first barrier; the
+// first barrier of a launch always uses kBarWorkgroup and, if any workgroup
+// of the team found another mapping, the launch stays on kBarWorkgroup.
+//
+// Every wait gives up when `fatal` is raised or its own wall-clock deadline
+// passes (raising `fatal` itself), so every wait ends.  Workgroup 0 reads
+// the optional host abort flag before it arrives; the barrier cannot
 // complete before that read, so a raised flag is seen by every waiting
 // workgroup as `fatal`.  Returns false when the caller must leave the loop.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kBarXcd = 0;
+constexpr uint32_t kBarWorkgroup = 1;
+constexpr uint32_t kBarXcdInv = 2;
+
 struct BarrierState {
     uint32_t epoch;               // barriers passed by this workgroup
     unsigned long long wd_ticks;  // watchdog in wall-clock ticks
+    uint32_t want;                // requested scheme (kBar*)
+    uint32_t kind;                // scheme in use (kBarWorkgroup until the mapping is checked)
 };
+
+__device__ __forceinline__ BarrierState make_barrier_state(unsigned long long wd_ticks, uint32_t want) {
+    return BarrierState{0u, wd_ticks, want, kBarWorkgroup};
+}
+
+// Barrier words of a fresh launch (one thread, before the launch that uses them).
+__device__ __forceinline__ void reset_barrier_words(Ctrl *c) {
+    c->bar_gen = 0;
+    c->bar_top = 0;
+    for (int g = 0; g < kBarGroups; ++g) {
+        c->bar_grp[g].count = 0;
+        c->bar_grp[g].gen = 0;
+    }
+    c->xmap_bad = 0;
+}
+
+// The XCD this wave runs on (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ uint32_t xcc_id() {
+    return static_cast<uint32_t>(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20)) & 15u;
+}
+
+// Drop this CU's vector L1 lines (the L2 is left alone).
+__device__ __forceinline__ void invalidate_l1() { asm volatile("buffer_inv sc0" ::: "memory"); }
 
 // The workgroups that cooperate on one query: the whole grid of a
 // single-query launch, or one group of a batched launch.  Grid-stride loops
@@ -221,6 +272,7 @@ __device__ __forceinline__ bool grid_barrier(Ctrl *ctrl, BarrierState &bs, int *
                                              const volatile int32_t *abort_flag, Team tm) {
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (bs.epoch == 0 && xcc_id() != blockIdx.x % kBarGroups) atomicOr(&ctrl->xmap_bad, 1u);
         if (abort_flag && tm.id == 0 &&
             __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
             set_error(ctrl, kErrAborted, true);
@@ -229,19 +281,33 @@ __device__ __forceinline__ bool grid_barrier(Ctrl *ctrl, BarrierState &bs, int *
         const uint32_t gid = tm.id % ngroups;
         const uint32_t gsize = G / ngroups + (gid < G % ngroups ? 1u : 0u);
         const uint32_t epoch = ++bs.epoch;
-        const unsigned long long old =
-            __hip_atomic_fetch_add(&ctrl->bar_grp[gid].count, 1ull, __ATOMIC_ACQ_REL,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        if (old + 1 == static_cast<unsigned long long>(epoch) * gsize) {
-            const unsigned long long top = __hip_atomic_fetch_add(
-                &ctrl->bar_top, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const bool per_xcd = bs.kind != kBarWorkgroup;
+        unsigned long long old;
+        if (per_xcd)
+            old = __hip_atomic_fetch_add(&ctrl->bar_grp[gid].count, 1ull, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        else
+            old = __hip_atomic_fetch_add(&ctrl->bar_grp[gid].count, 1ull, __ATOMIC_ACQ_REL,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        const bool last = old + 1 == static_cast<unsigned long long>(epoch) * gsize;
+        if (last) {
+            unsigned long long top;
+            if (per_xcd) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write back this XCD's L2
+                top = __hip_atomic_fetch_add(&ctrl->bar_top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                top = __hip_atomic_fetch_add(&ctrl->bar_top, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            }
             if (top + 1 == static_cast<unsigned long long>(epoch) * ngroups)
                 __hip_atomic_store(&ctrl->bar_gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
+        // kBarXcdInv: only the group's last arrival waits for the generation
+        const bool group_wait = bs.kind == kBarXcdInv && !last;
+        const uint32_t *word = group_wait ? &ctrl->bar_grp[gid].gen : &ctrl->bar_gen;
+        int ok = 1;
         const unsigned long long t0 = wall_clock64();
-        while (__hip_atomic_load(&ctrl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-            __builtin_amdgcn_s_sleep(2);
+        while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            __builtin_amdgcn_s_sleep(1);
             if (load_agent(&ctrl->fatal)) {
                 ok = 0;
                 break;
@@ -252,7 +318,15 @@ __device__ __forceinline__ bool grid_barrier(Ctrl *ctrl, BarrierState &bs, int *
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (group_wait) {
+            invalidate_l1();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (bs.kind == kBarXcdInv)
+                __hip_atomic_store(&ctrl->bar_grp[gid].gen, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // after the first barrier every workgroup's mapping check is visible
+        if (epoch == 1) bs.kind = load_agent(&ctrl->xmap_bad) ? kBarWorkgroup : bs.want;
         *s_flag = ok;
     }
     __syncthreads();

@@ -24,6 +24,9 @@ struct Pushers {
     Sink sk;
     Sink skf;
     uint32_t fmin;            // this lane's far-list lower bound since the last drain
+    const int32_t *deg_rp;    // BFS direction choice: row offsets to sum pushed degrees, or null
+    unsigned long long *mf_out;
+    unsigned long long mf;    // this lane's sum of out-degrees of pushed vertices
     __device__ __forceinline__ void near(bool p, int item) {
         nq.push(p, item, sk.cnt_out, sk.out, sk.cap, sk.ctrl);
     }
@@ -36,6 +39,14 @@ struct Pushers {
 template <int B, class Op, class S>
 __device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
     block_drain<B, kQueueCap>(pu.nq, sm.fill, &sm.base, pu.sk.cnt_out, pu.sk.out, pu.sk.cap, pu.sk.ctrl);
+    if (pu.deg_rp) {
+        // one atomicAdd per wavefront: out-degree sum of the pushed vertices
+        unsigned long long x = pu.mf;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) x += __shfl_xor(x, d, kWave);
+        if (lane_id() == 0 && x) atomicAdd(pu.mf_out, x);
+        pu.mf = 0;
+    }
     if (Op::kFar) {
         block_drain<B, kQueueCap>(pu.fq, sm.fill, &sm.base, pu.skf.cnt_out, pu.skf.out, pu.skf.cap,
                                   pu.skf.ctrl);
@@ -69,6 +80,11 @@ __device__ __forceinline__ void relax_and_push(const Op &op, const int32_t *__re
         far[k] = false;
     }
     op.relax(e, d, sv, sval, act, far, pu.fmin);
+    if (!Op::kFar && pu.deg_rp) {
+#pragma unroll
+        for (int k = 0; k < kU; ++k)
+            if (act[k]) pu.mf += static_cast<unsigned long long>(pu.deg_rp[d[k] + 1] - pu.deg_rp[d[k]]);
+    }
     if (Op::kPush) {
 #pragma unroll
         for (int k = 0; k < kU; ++k) pu.near(act[k], d[k]);
@@ -108,10 +124,10 @@ __device__ __forceinline__ void stride_range(const Op &op, const int32_t *__rest
 // ---------------------------------------------------------------------------
 // Phase A of one invocation: nested-parallel expansion of the incoming
 // worklist.  `in == nullptr` means the identity worklist 0..cnt_in-1.
-// Vertices of out-degree >= t_grid (t_grid > 0) are appended to the
-// grid-tier list (hub_v / hub_base, counted by *hub_ctr) instead of being
-// expanded here.  Every thread of every workgroup must call it (it
-// synchronises the workgroup).
+// Vertices of out-degree >= t_grid (t_grid > 0; t_block for a small
+// worklist) are appended to the grid-tier list (hub_v / hub_base, counted by
+// *hub_ctr) instead of being expanded here.  Every thread of every workgroup
+// must call it (it may synchronise the workgroup).
 // ---------------------------------------------------------------------------
 template <int B, class Op>
 __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t cnt_in, uint32_t n,
@@ -127,6 +143,45 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
     const int lane = lane_id();
     const int wid = tid / kWave;
     const uint32_t stride = tm.size * B;
+
+    // Small worklist (no more items than wavefronts in the team): one item per
+    // wavefront, dealt across workgroups first, so that the ranges of a few
+    // items are not walked one after another by a few workgroups.  Ranges of
+    // t_block or more edges go to the grid tier.
+    if (t_grid > 0 && cnt_in <= tm.size * NW) {
+        const uint32_t i = static_cast<uint32_t>(wid) * tm.size + tm.id;
+        if (i >= cnt_in) return;  // uniform across the wavefront
+        int v = in ? in[i] : static_cast<int>(i);
+        int r0 = 0, r1 = 0;
+        uint32_t val = 0;
+        if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
+            if (lane == 0) set_error(pu.sk.ctrl, kErrInternal, false);
+            return;
+        }
+        val = op.vertex_value(v);
+        if (op.active(val)) {
+            r0 = row_ptr[v];
+            r1 = row_ptr[v + 1];
+        }
+        const int deg = r1 - r0;
+        if (lane == 0) edges += static_cast<unsigned long long>(deg);
+        if (deg >= t_block) {
+            int listed = 0;
+            if (lane == 0) {
+                const unsigned long long old = atomicAdd(
+                    hub_ctr, (1ull << 40) | static_cast<unsigned long long>((deg + kChunk - 1) / kChunk));
+                const uint32_t slot = static_cast<uint32_t>(old >> 40);
+                if (slot < hub_cap) {
+                    hub_v[slot] = v;
+                    hub_base[slot] = static_cast<uint32_t>(old & ((1ull << 40) - 1));
+                    listed = 1;
+                }
+            }
+            if (__shfl(listed, 0, kWave)) return;
+        }
+        stride_range(op, col, r0, r1, v, val, lane, kWave, pu);
+        return;
+    }
 
     for (uint32_t base = tm.id * B; base < cnt_in; base += stride) {
         const uint32_t i = base + tid;

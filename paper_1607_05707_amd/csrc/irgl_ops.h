@@ -53,9 +53,10 @@ struct Params {
     int32_t src;
     uint32_t it;          // host-loop mode: the invocation to run
     unsigned long long wd_ticks;
+    uint32_t barrier;  // grid-barrier coherence scheme (kBar*)
     const volatile int32_t *abort_flag;
-    uint32_t *visited;    // BFS visited bitmap, ceil(n / 32) words
-    uint32_t t_bitmap;    // refresh the bitmap when the incoming worklist is this large
+    uint32_t *visited;    // BFS visited / SSSP settled bitmap, ceil(n / 32) words
+    uint32_t t_bitmap;    // refresh it once this many new items were popped since the last refresh
     uint32_t trace_len;
     unsigned long long *trace;
     int32_t *far0;        // SSSP far lists (two buffers), n entries each
@@ -65,6 +66,11 @@ struct Params {
     uint32_t delta;       // SSSP threshold step (INF: plain Bellman-Ford)
     uint32_t thresh;      // host-loop mode: current threshold
     uint32_t far_tr;      // host-loop mode: threshold raises so far
+    uint32_t refresh;     // host-loop mode: refresh the bitmap in this invocation
+    uint32_t *frontier;   // BFS bottom-up: bitmap of the current frontier, or null (top-down only)
+    uint32_t do_alpha;    // BFS direction choice (see irgl_config)
+    uint32_t do_beta;
+    long long m;          // edges of the graph
 };
 
 // ---------------------------------------------------------------------------
@@ -127,12 +133,21 @@ struct SsspOp {
     uint32_t thresh;
     uint32_t it;
     Ctrl *ctrl;
+    const uint32_t *settled;  // bitmap of vertices whose distance is final, or null
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],
                                           const uint32_t (&dv)[kU], bool (&act)[kU],
                                           bool (&far)[kU], uint32_t &fmin) const {
         uint32_t nd[kU], cur[kU];
+        // a settled destination cannot improve (weights >= 1): skip it with an
+        // L2-resident bit test instead of a probe of dist[]
+        if (settled) {
+#pragma unroll
+            for (int k = 0; k < kU; ++k) cur[k] = act[k] ? settled[static_cast<uint32_t>(d[k]) >> 5] : 0u;
+#pragma unroll
+            for (int k = 0; k < kU; ++k) act[k] = act[k] && !(cur[k] & (1u << (d[k] & 31)));
+        }
 #pragma unroll
         for (int k = 0; k < kU; ++k) nd[k] = act[k] ? w[e[k]] : 0u;
         bool ovf = false;

@@ -42,11 +42,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
             c->far_cnt[k] = 0;
             c->far_min[k] = kInf;
         }
-        if (reset_barrier) {
-            c->bar_gen = 0;
-            c->bar_top = 0;
-            for (int g = 0; g < kBarGroups; ++g) c->bar_grp[g].count = 0;
-        }
+        if (reset_barrier) reset_barrier_words(c);
         c->error = 0;
         c->fatal = 0;
         c->done = 0;
@@ -54,6 +50,10 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
         c->max_frontier = 0;
         c->items = 0;
         c->edges = 0;
+        c->fedges = 0;
+        c->mf[0] = static_cast<unsigned long long>(p.row_ptr[p.src + 1] - p.row_ptr[p.src]);
+        c->mf[1] = 0;
+        c->mf[2] = 0;
         p.wl0[0] = p.src;
 }
 
@@ -67,7 +67,7 @@ __device__ __forceinline__ Op make_op(const Params &p, uint32_t it, uint32_t thr
 
 template <>
 __device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh) {
-    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl};
+    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited};
 }
 
 template <>
@@ -75,16 +75,18 @@ __device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it, ui
     return BfsOp{p.val, p.parent, p.visited, it + 1};
 }
 
-// Refresh the BFS visited bitmap from the level array: one ballot per 64
+// Refresh a vertex bitmap from the value array: bit v = (val[v] < below).
+// BFS: below = INF gives "visited"; SSSP: below = the threshold whose near
+// phase has drained gives "settled" (final distance).  One ballot per 64
 // consecutive vertices, coalesced reads, one plain word store per 32
 // vertices.  Readers may see old or new words concurrently; both only ever
-// mark visited vertices, so any mix is a valid filter.
-__device__ __forceinline__ void refresh_bitmap(const Params &p, Team tm) {
+// mark vertices that qualify, so any mix is a valid filter.
+__device__ __forceinline__ void refresh_bitmap(const Params &p, Team tm, uint32_t below) {
     const uint32_t n = static_cast<uint32_t>(p.n);
     const uint32_t stride = tm.size * blockDim.x;
     for (uint32_t base = tm.id * blockDim.x; base < n; base += stride) {
         const uint32_t v = base + threadIdx.x;
-        const bool vis = v < n && p.val[v] != kInf;
+        const bool vis = v < n && p.val[v] < below;
         const unsigned long long m = __ballot(vis);
         const int lane = lane_id();
         const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
@@ -93,13 +95,7 @@ __device__ __forceinline__ void refresh_bitmap(const Params &p, Team tm) {
     }
 }
 
-template <class Op>
-__device__ __forceinline__ void level_prologue(const Params &, uint32_t, Team) {}
 
-template <>
-__device__ __forceinline__ void level_prologue<BfsOp>(const Params &p, uint32_t cnt_in, Team tm) {
-    if (p.visited && cnt_in >= p.t_bitmap) refresh_bitmap(p, tm);
-}
 
 // Write the control block's statistics to the caller's stats block.
 __device__ __forceinline__ void publish_stats(const Params &p) {
@@ -114,6 +110,7 @@ __device__ __forceinline__ void publish_stats(const Params &p) {
     s->grid = c->grid;
     s->block = c->block;
     s->reserved = 0;
+    s->frontier_edges = __hip_atomic_load(&c->fedges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum a per-thread counter over the workgroup and add it to *dst.
@@ -165,6 +162,73 @@ __device__ __forceinline__ uint32_t next_threshold(uint32_t thresh, uint32_t far
     return raise_threshold(max(thresh, far_min), delta);
 }
 
+
+// ---------------------------------------------------------------------------
+// BFS bottom-up invocation (direction optimization on a symmetric graph): a
+// topology-driven ForAll over the vertices, where every unvisited vertex
+// looks through its own neighbours for one in the current frontier and stops
+// at the first hit.  Each vertex is decided by exactly one lane, so labels
+// need no atomics; found vertices are pushed as usual so that a following
+// top-down invocation has its worklist.
+// ---------------------------------------------------------------------------
+
+// Bitmaps for a bottom-up invocation at level `cur`: frontier = (level == cur),
+// visited = (level != INF).  One ballot pair per 64 consecutive vertices.
+__device__ __forceinline__ void build_pull_bitmaps(const Params &p, uint32_t cur, Team tm) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    const uint32_t stride = tm.size * blockDim.x;
+    for (uint32_t base = tm.id * blockDim.x; base < n; base += stride) {
+        const uint32_t v = base + threadIdx.x;
+        const uint32_t lv = v < n ? p.val[v] : kInf;
+        const unsigned long long mv = __ballot(lv != kInf);
+        const unsigned long long mfr = __ballot(lv == cur);
+        const int lane = lane_id();
+        const uint32_t v0 = v - static_cast<uint32_t>(lane);
+        if (lane == 0 && v0 < n) {
+            p.visited[v0 >> 5] = static_cast<uint32_t>(mv);
+            p.frontier[v0 >> 5] = static_cast<uint32_t>(mfr);
+        }
+        if (lane == 32 && v < n) {
+            p.visited[v >> 5] = static_cast<uint32_t>(mv >> 32);
+            p.frontier[v >> 5] = static_cast<uint32_t>(mfr >> 32);
+        }
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team tm, Pushers &pu,
+                                           unsigned long long &scanned) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    for (uint32_t base = tm.id * B; base < n; base += tm.size * B) {
+        const uint32_t v = base + threadIdx.x;
+        int r0 = 0, r1 = 0;
+        if (v < n && !((p.visited[v >> 5] >> (v & 31)) & 1u)) {
+            r0 = p.row_ptr[v];
+            r1 = p.row_ptr[v + 1];
+        }
+        int found = -1;
+        for (int e0 = r0; e0 < r1; e0 += kU) {
+            int u[kU];
+            uint32_t fw[kU];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
+#pragma unroll
+            for (int k = 0; k < kU; ++k) fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
+#pragma unroll
+            for (int k = 0; k < kU; ++k)
+                if (found < 0 && u[k] >= 0 && ((fw[k] >> (u[k] & 31)) & 1u)) found = u[k];
+            scanned += static_cast<unsigned long long>(min(kU, r1 - e0));
+            if (found >= 0) break;
+        }
+        if (found >= 0) {
+            p.val[v] = next;
+            if (p.parent) p.parent[v] = found;
+            pu.mf += static_cast<unsigned long long>(r1 - r0);
+        }
+        pu.near(found >= 0, static_cast<int>(v));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The outlined Iterate loop, run by one team (the whole grid of a
 // single-query launch, or one group of a batched launch).  An invocation that
@@ -177,8 +241,9 @@ __device__ __forceinline__ uint32_t next_threshold(uint32_t thresh, uint32_t far
 struct LoopResult {
     uint32_t iterations;
     unsigned long long items;
-    unsigned long long edges;  // CSR entries this workgroup scanned
+    unsigned long long edges;   // CSR entries this workgroup scanned
     uint32_t max_frontier;
+    unsigned long long fedges;  // out-degree sums of the worklists (this workgroup's share)
 };
 
 template <int B, class Op>
@@ -187,13 +252,21 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     const int wid = tid / kWave;
     Ctrl *ctrl = p.ctrl;
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, {}, {}, kInf};
-    LoopResult r{0u, 0ull, 0ull, 0u};
+    LoopResult r{0u, 0ull, 0ull, 0u, 0ull};
+    // BFS direction choice (needs the frontier bitmap; symmetric graphs only)
+    const bool can_pull = !Op::kFar && p.frontier != nullptr;
+    bool pull = false;
+    unsigned long long m_seen = 0;  // out-degree sum of all worklists so far
+    if (can_pull) pu.deg_rp = p.row_ptr;
     const int32_t *in = p.wl0;
     int32_t *out = p.wl1;
     uint32_t it = 0;
     uint32_t tr = 0;                              // threshold raises so far
     uint32_t thresh = Op::kFar ? p.delta : kInf;  // near/far split point
     const bool lead = tm.id == 0 && tid == 0;
+    // popped items when the bitmap was last refreshed: refresh again once the
+    // newly reached vertices carry enough edges to repay a full scan
+    unsigned long long refreshed = 0;
 
     for (;; ++it) {
         uint32_t cnt_in = load_agent(&ctrl->cnt[it % 3]);
@@ -213,6 +286,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
         if (lead) {
             store_agent(&ctrl->cnt[(it + 2) % 3], 0u);
             __hip_atomic_store(&ctrl->hub[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctrl->mf[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (cnt_in == 0) {
                 store_agent(&ctrl->far_cnt[(tr + 2) % 3], 0u);
                 store_agent(&ctrl->far_min[(tr + 2) % 3], kInf);
@@ -229,6 +303,10 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
         if (cnt_in == 0) {
             // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1
             const uint32_t t_new = next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta);
+            if (p.visited && r.items - refreshed >= p.t_bitmap) {
+                refresh_bitmap(p, tm, thresh);  // every distance below thresh is final
+                refreshed = r.items;
+            }
             pu.skf = far_sink(p, tr + 1);
             far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), thresh, t_new,
                             p.val, p.far_flag, pu, tm);
@@ -236,10 +314,36 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
             thresh = t_new;
             ++tr;
+        } else if (can_pull && ([&] {
+                       // uniform: the settled out-degree sum of this worklist
+                       const unsigned long long m_f = __hip_atomic_load(&ctrl->mf[it % 3], __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                       m_seen += m_f;
+                       const long long m_u = p.m - static_cast<long long>(m_seen);
+                       if (!pull) pull = static_cast<long long>(m_f) * p.do_alpha > m_u;
+                       else pull = static_cast<unsigned long long>(cnt_in) * p.do_beta >=
+                                   static_cast<unsigned long long>(p.n);
+                       if (pull && tid == 0 && tm.id == 0) r.fedges += m_f;
+                       return pull;
+                   }())) {
+            // bottom-up invocation: bitmaps, barrier, pull
+            pu.mf_out = &ctrl->mf[(it + 1) % 3];
+            build_pull_bitmaps(p, it, tm);
+            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            const unsigned long long edges_before = r.edges;
+            pull_level<B>(p, it + 1, tm, pu, r.edges);
+            refreshed = r.items;  // the visited bitmap was rebuilt for this invocation
+            drain_all<B, Op>(pu, sm);
+            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
         } else {
             pu.skf = far_sink(p, tr);
+            pu.mf_out = &ctrl->mf[(it + 1) % 3];
             const unsigned long long edges_before = r.edges;
-            level_prologue<Op>(p, cnt_in, tm);
+            if (!Op::kFar && p.visited && r.items - refreshed >= p.t_bitmap) {
+                refresh_bitmap(p, tm, kInf);  // BFS: visited = labelled
+                refreshed = r.items;
+            }
             const Op op = make_op<Op>(p, it, thresh);
             expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
                           p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm);
@@ -255,6 +359,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                     if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
                 }
             }
+            r.fedges += r.edges - edges_before;
             if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
         }
         const int32_t *t = in;
@@ -271,6 +376,7 @@ template <int B>
 __device__ __forceinline__ void finish_query(const Params &p, const LoopResult &r, Team tm) {
     Ctrl *ctrl = p.ctrl;
     add_block_total<B>(r.edges, &ctrl->edges);
+    add_block_total<B>(r.fedges, &ctrl->fedges);
     if (threadIdx.x == 0) {
         if (tm.id == 0) {
             if (4 * r.iterations < p.trace_len) p.trace[4 * r.iterations] = wall_clock64();
@@ -294,7 +400,7 @@ template <int B, class Op>
 __global__ __launch_bounds__(B) void persistent_kernel(Params p) {
     __shared__ Smem<B> sm;
     const Team tm = whole_grid();
-    BarrierState bs{0u, p.wd_ticks};
+    BarrierState bs = make_barrier_state(p.wd_ticks, p.barrier);
     const LoopResult r = run_iterate<B, Op>(p, sm, tm, bs);
     finish_query<B>(p, r, tm);
 }
@@ -325,12 +431,13 @@ __global__ __launch_bounds__(B) void level_kernel(Params p) {
         p.trace[4 * it] = wall_clock64();
         p.trace[4 * it + 1] = cnt_in;
     }
-    level_prologue<Op>(p, cnt_in, whole_grid());
+    if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), kInf);
     const Op op = make_op<Op>(p, it, p.thresh);
     expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave, p.t_block,
                   p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges, whole_grid());
     drain_all<B, Op>(pu, sm);
     add_block_total<B>(edges, &ctrl->edges);
+    add_block_total<B>(edges, &ctrl->fedges);  // top-down only: every worklist edge is scanned
     if (tid == 0 && blockIdx.x == 0) {
         ctrl->cnt[(it + 2) % 3] = 0;
         ctrl->hub[(it + 2) % 3] = 0;
@@ -375,6 +482,7 @@ __global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, u
         p.trace[4 * it] = wall_clock64();
         p.trace[4 * it + 1] = 0;
     }
+    if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), p.thresh);
     far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), p.thresh, t_new, p.val,
                     p.far_flag, pu, whole_grid());
     drain_all<B, SsspOp>(pu, sm);

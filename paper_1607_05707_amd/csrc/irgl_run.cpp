@@ -4,10 +4,14 @@
 //
 //   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
 //                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
+//                 [--do-alpha A] [--delta D] [--calibrate MB]
+//
+// --calibrate MB first copies MB megabytes device-to-device once (a plain
+// copy of known traffic, to scale hardware byte counters).
 //
 // Prints one line per kind: queries, mean microseconds per query (hipEvent
-// pairs around each call on one stream) and GTEPS (edges scanned by the BFS
-// from each source / time).
+// pairs around each call on one stream) and GTEPS (out-degree sum of the
+// vertices a BFS from each source reaches / time).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -42,6 +46,7 @@ int main(int argc, char **argv) {
     }
     std::string kinds = "bfs,sssp";
     int nsrc = 8, reps = 1, warmup = 1;
+    long calib_mb = 0;
     irgl_config cfg;
     std::memset(&cfg, 0, sizeof(cfg));
     for (int i = 2; i + 1 < argc; i += 2) {
@@ -55,6 +60,9 @@ int main(int argc, char **argv) {
         else if (k == "--mode") cfg.mode = std::atoi(v);
         else if (k == "--t-grid") cfg.t_grid = std::atoi(v);
         else if (k == "--t-bitmap") cfg.t_bitmap = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--do-alpha") cfg.do_alpha = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--delta") cfg.delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--calibrate") calib_mb = std::atol(v);
         else {
             std::fprintf(stderr, "unknown option %s\n", k.c_str());
             return 2;
@@ -72,7 +80,7 @@ int main(int argc, char **argv) {
         std::fprintf(stderr, "bad file header\n");
         return 1;
     }
-    const int64_t n = hdr[0], m = hdr[1], has_w = hdr[2], ns = hdr[3];
+    const int64_t n = hdr[0], m = hdr[1], has_w = hdr[2] & 1, symmetric = (hdr[2] >> 1) & 1, ns = hdr[3];
     if (n <= 0 || n >= (int64_t(1) << 31) || m < 0 || m >= (int64_t(1) << 31) || ns <= 0) {
         std::fprintf(stderr, "bad sizes\n");
         return 1;
@@ -89,6 +97,19 @@ int main(int argc, char **argv) {
         return 1;
     }
     if (nsrc > ns) nsrc = static_cast<int>(ns);
+    if (calib_mb > 0) {
+        const size_t bytes = static_cast<size_t>(calib_mb) << 20;
+        void *a, *b;
+        CK(hipMalloc(&a, bytes));
+        CK(hipMalloc(&b, bytes));
+        CK(hipMemset(a, 1, bytes));
+        CK(hipDeviceSynchronize());
+        CK(hipMemcpy(b, a, bytes, hipMemcpyDeviceToDevice));
+        CK(hipDeviceSynchronize());
+        std::printf("calibration copy: %zu bytes read + %zu bytes written\n", bytes, bytes);
+        CK(hipFree(a));
+        CK(hipFree(b));
+    }
 
     int32_t *d_rp, *d_col, *d_out;
     uint32_t *d_w = nullptr;
@@ -101,7 +122,7 @@ int main(int argc, char **argv) {
         CK(hipMalloc(&d_w, m * 4 + 4));
         CK(hipMemcpy(d_w, w.data(), m * 4, hipMemcpyHostToDevice));
     }
-    irgl_csr csr{static_cast<int32_t>(n), m, d_rp, d_col, d_w, IRGL_VALIDATE};
+    irgl_csr csr{static_cast<int32_t>(n), m, d_rp, d_col, d_w, IRGL_VALIDATE | (symmetric ? IRGL_SYMMETRIC : 0u)};
     irgl_graph g;
     CI(irgl_graph_upload(&csr, &g));
     irgl_stats *d_stats;
@@ -124,7 +145,7 @@ int main(int argc, char **argv) {
                                          : irgl_sssp(g, sv, reinterpret_cast<uint32_t *>(d_out), nullptr, ws,
                                                      wsb, s, d_stats, &cfg);
         };
-        if (kind == IRGL_KIND_BFS) {  // numerator: edges scanned from each source
+        if (kind == IRGL_KIND_BFS) {  // numerator: out-degree sum of the reached vertices
             for (int i = 0; i < nsrc; ++i) {
                 CI(run(src[i]));
                 irgl_stats st;
@@ -133,7 +154,7 @@ int main(int argc, char **argv) {
                     std::fprintf(stderr, "bfs from %d: %s\n", src[i], irgl_status_string(st.status));
                     return 1;
                 }
-                mcc[i] = st.edges;
+                mcc[i] = st.frontier_edges;
             }
         }
         for (int r = 0; r < warmup; ++r)

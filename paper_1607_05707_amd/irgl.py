@@ -46,6 +46,10 @@ IRGL_WATCHDOG_IMMEDIATE = 0xFFFFFFFF
 IRGL_BITMAP_NEVER = 0xFFFFFFFF
 IRGL_GRID_TIER_OFF = -1
 IRGL_DELTA_NONE = 0xFFFFFFFF
+IRGL_DO_OFF = 0xFFFFFFFF
+IRGL_BARRIER_XCD = 0
+IRGL_BARRIER_WORKGROUP = 1
+IRGL_BARRIER_XCD_INV = 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
@@ -63,14 +67,16 @@ class irgl_config(ctypes.Structure):
                 ("t_grid", ctypes.c_int32), ("grid", ctypes.c_int32), ("mode", ctypes.c_int32), ("max_iter", ctypes.c_uint32),
                 ("wl_capacity", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
                 ("abort_flag", ctypes.c_void_p), ("t_bitmap", ctypes.c_uint32),
-                ("trace_len", ctypes.c_uint32), ("delta", ctypes.c_uint32), ("trace", ctypes.c_void_p)]
+                ("trace_len", ctypes.c_uint32), ("do_alpha", ctypes.c_uint32), ("do_beta", ctypes.c_uint32),
+                ("delta", ctypes.c_uint32), ("trace", ctypes.c_void_p), ("barrier", ctypes.c_uint32)]
 
 
 class irgl_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_uint32),
                 ("items", ctypes.c_uint64), ("edges", ctypes.c_uint64),
                 ("max_frontier", ctypes.c_uint32), ("grid", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+                ("block", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("frontier_edges", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -334,7 +340,8 @@ class irgl_task(ctypes.Structure):
 class irgl_batch_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("team", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("t_grid", ctypes.c_int32), ("delta", ctypes.c_uint32),
-                ("watchdog_ms", ctypes.c_uint32), ("grid", ctypes.c_int32)]
+                ("watchdog_ms", ctypes.c_uint32), ("grid", ctypes.c_int32), ("barrier", ctypes.c_uint32),
+                ("gang_edges", ctypes.c_uint32)]
 
 
 _lib.irgl_control_block_sizes.restype = ctypes.c_int32
@@ -511,9 +518,16 @@ class Server:
 
 
 def irgl_batch_open(graphs, cfg=None, ring_cap: int = 256, idle_ms: int = 50, ws=None, stream=None) -> Server:
+    """The server kernel keeps its stream busy while it runs, so by default it
+    gets a stream of its own (default priority), ordered after the caller's
+    current stream.  Task buffers are written as soon as a task is queued: the
+    caller finishes its own pending work on them first."""
+    dev = graphs[0].row_ptr.device
     if ws is None:
-        ws = torch.empty(irgl_batch_open_bytes(graphs, cfg, ring_cap), dtype=torch.uint8,
-                         device=graphs[0].row_ptr.device)
+        ws = torch.empty(irgl_batch_open_bytes(graphs, cfg, ring_cap), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.Stream(device=dev)
+        stream.wait_stream(torch.cuda.current_stream(dev))
     c = make_batch_config(cfg)
     h = ctypes.c_void_p()
     _check(_lib.irgl_batch_open(_graph_array(graphs), len(graphs), ctypes.byref(c) if c is not None else None,

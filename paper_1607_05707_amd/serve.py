@@ -146,6 +146,8 @@ def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap:
                     raise RuntimeError(f"query {qi} failed: {irgl.irgl_status_string(st['status'])}")
                 if keep_outputs is not None and qi in keep_outputs:
                     kept[qi] = task.out.clone()
+                    # the buffer is recycled by the allocator once the task is dropped
+                    torch.cuda.current_stream(dev).synchronize()
                 used -= need
                 done_count += 1
         if not inflight and not pending and nxt < len(queries):

@@ -8,9 +8,9 @@ Workloads (all seeded, see graphgen):
                   weights U[1,10000], source 0 + 8 random
   road4096_nolong the same without long edges (high diameter)
 
-File format (little endian): b"IRGLCSR1", int64 n, int64 m, int64 has_w,
-int64 nsrc, int32 row_ptr[n+1], int32 col[m], uint32 w[m] (if has_w),
-int32 sources[nsrc].
+File format (little endian): b"IRGLCSR1", int64 n, int64 m, int64 flags
+(bit 0: weights present, bit 1: symmetric), int64 nsrc, int32 row_ptr[n+1],
+int32 col[m], uint32 w[m] (if bit 0), int32 sources[nsrc].
 """
 from __future__ import annotations
 
@@ -50,7 +50,8 @@ def write_csr(path: str, g) -> None:
     src = np.asarray(g.sources or [0], dtype=np.int32)
     with open(path, "wb") as f:
         f.write(MAGIC)
-        f.write(np.array([g.n, g.m, 0 if w is None else 1, src.size], dtype=np.int64).tobytes())
+        flags = (0 if w is None else 1) | (2 if getattr(g, "symmetric", False) else 0)
+        f.write(np.array([g.n, g.m, flags, src.size], dtype=np.int64).tobytes())
         f.write(np.ascontiguousarray(rp, dtype=np.int32).tobytes())
         f.write(np.ascontiguousarray(col, dtype=np.int32).tobytes())
         if w is not None:

@@ -52,11 +52,12 @@ def _make_tasks(irgl, graphs, per_graph, with_parent, seed):
     return tasks, meta
 
 
-@pytest.mark.parametrize("team,block", [(16, 256), (1, 256), (4, 512), (10_000, 256)])
-def test_batch_matches_oracle(irgl, graphs, team, block):
+@pytest.mark.parametrize("team,block,barrier", [(16, 256, 0), (1, 256, 0), (4, 512, 0), (10_000, 256, 0),
+                                                (16, 256, 1), (16, 256, 2), (3, 256, 2), (10_000, 256, 2)])
+def test_batch_matches_oracle(irgl, graphs, team, block, barrier):
     tasks, meta = _make_tasks(irgl, graphs, per_graph=5, with_parent=(team == 16), seed=team)
-    print(f"[case] batch team={team} block={block} tasks={len(tasks)}", flush=True)
-    b = irgl.irgl_batch_submit(tasks, cfg={"team": team, "block": block})
+    print(f"[case] batch team={team} block={block} barrier={barrier} tasks={len(tasks)}", flush=True)
+    b = irgl.irgl_batch_submit(tasks, cfg={"team": team, "block": block, "barrier": barrier})
     stats = irgl.irgl_batch_wait(b)
     for t, (gi, kind, s), st in zip(tasks, meta, stats):
         g, hg, np_g = graphs[gi]
@@ -69,6 +70,7 @@ def test_batch_matches_oracle(irgl, graphs, team, block):
             oracle.validate(rp, col, s, got, t.parent.cpu().numpy(), None if kind == BFS else w)
         if kind == BFS:
             assert st["iterations"] == int(ref[ref != oracle.INF].max()) + 1
+            assert st["frontier_edges"] == oracle.edges_scanned(np_g[0], ref)
     b.free()
 
 

@@ -41,8 +41,10 @@ def _check_query(irgl, g, hg, kind, src, cfg=None, with_parent=True, ref=None):
         oracle.validate(rp, col, src, got, par.cpu().numpy(), None if kind == BFS else w)
     if kind == BFS:
         assert st["iterations"] == int(ref[ref != oracle.INF].max()) + 1
-        assert st["edges"] == oracle.edges_scanned(rp, ref)
+        assert st["frontier_edges"] == oracle.edges_scanned(rp, ref)
         assert st["items"] == int((ref != oracle.INF).sum())
+        if not (cfg or {}).get("do_alpha") and not g.symmetric:
+            assert st["edges"] == st["frontier_edges"]  # top-down scans every frontier edge
     assert st["status"] == 0
     return got, st
 
@@ -91,6 +93,26 @@ def test_sssp_near_far_deltas(irgl, delta):
     _check_query(irgl, r, hr, SSSP, r.sources[1], {"delta": delta})
 
 
+@pytest.mark.parametrize("scale", [12, 15])
+def test_bfs_direction_optimized(irgl, scale):
+    """Bottom-up invocations (symmetric graphs) give the same levels, valid
+    parents, and fewer scanned edges than the top-down-only run."""
+    g = _dev(gg.rmat(scale, seed=40 + scale, weight_seed=1))
+    hg = irgl.upload(g)
+    for src in gg.pick_sources(g, 3, seed=scale):
+        _, st_do = _check_query(irgl, g, hg, BFS, src, {"do_alpha": 14, "do_beta": 24})
+        _, st_td = _check_query(irgl, g, hg, BFS, src, {"do_alpha": 0xFFFFFFFF})
+        _check_query(irgl, g, hg, BFS, src, {"do_alpha": 1, "do_beta": 1, "block": 1024})
+        assert st_td["edges"] == st_td["frontier_edges"]
+        if scale >= 15:
+            assert st_do["edges"] < st_td["edges"]
+    # a directed graph never pulls (in-edges unknown): same as top-down
+    d = _dev(gg.random_directed(3000, 30000, seed=1, weight_seed=2))
+    hd = irgl.upload(d)
+    _, st = _check_query(irgl, d, hd, BFS, 0, {"do_alpha": 1})
+    assert st["edges"] == st["frontier_edges"]
+
+
 def test_tiny_random_graphs(irgl):
     rng = np.random.default_rng(77)
     for i in range(40):
@@ -120,6 +142,52 @@ def test_star_hub_and_long_path(irgl):
     hp = irgl.upload(gp)
     _check_query(irgl, gp, hp, BFS, 0)
     _check_query(irgl, gp, hp, SSSP, k // 3)
+
+
+def test_small_frontier_wave_per_item_and_hub_overflow(irgl):
+    """A worklist with no more items than wavefronts is dealt one item per
+    wavefront; its ranges of t_block or more edges go to the grid tier, and
+    those beyond the grid-tier list's capacity (m / t_grid + 1) are expanded
+    by their wavefront."""
+    rng = np.random.default_rng(11)
+    degs = [100, 300, 700, 1500, 2500, 5000]
+    src, dst = [], []
+    nxt = 61
+    for i in range(1, 61):
+        src.append(0)
+        dst.append(i)
+        d = degs[i % len(degs)]
+        src += [i] * d
+        dst += list(range(nxt, nxt + d))
+        nxt += d
+    n = nxt
+    # cross edges among the leaves, so that the third level is not a tree
+    a = rng.integers(61, n, 20000).tolist()
+    b = rng.integers(61, n, 20000).tolist()
+    src += a
+    dst += b
+    w = rng.integers(1, 50, len(src)).tolist()
+    g = _dev(gg.from_edges(n, src, dst, w, name="two_level"))
+    hg = irgl.upload(g)
+    for cfg in (None, {"block": 512}, {"block": 256, "mode": 1}, {"t_grid": 4096}):
+        _check_query(irgl, g, hg, BFS, 0, cfg)
+        _check_query(irgl, g, hg, SSSP, 0, cfg)
+
+
+@pytest.mark.parametrize("barrier", [0, 1, 2])
+def test_barrier_schemes(irgl, barrier):
+    """Per-XCD and per-workgroup barrier coherence give identical results,
+    over many barriers (near/far SSSP with a small step) and every block size."""
+    g = _dev(gg.rmat(14, seed=31, weight_seed=32, wmax=255))
+    hg = irgl.upload(g)
+    for src in gg.pick_sources(g, 2, seed=33):
+        for block in (256, 512, 1024):
+            _check_query(irgl, g, hg, BFS, src, {"barrier": barrier, "block": block})
+            _check_query(irgl, g, hg, SSSP, src, {"barrier": barrier, "block": block, "delta": 16})
+    r = _dev(gg.config_road(width=128))
+    hr = irgl.upload(r)
+    _check_query(irgl, r, hr, SSSP, r.sources[1], {"barrier": barrier, "delta": 50})
+    _check_query(irgl, r, hr, BFS, r.sources[2], {"barrier": barrier, "grid": 37})
 
 
 def test_road_grid_small(irgl):
@@ -172,6 +240,9 @@ def test_error_paths(irgl):
     assert e.value.status == irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
     with pytest.raises(irgl.IrglError) as e:
         irgl.irgl_bfs(hg, src, out, None, ws, cfg={"block": 384})
+    assert e.value.status == irgl.IRGL_ERR_CONFIG
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_bfs(hg, src, out, None, ws, cfg={"barrier": 3})
     assert e.value.status == irgl.IRGL_ERR_CONFIG
     gu = irgl.irgl_graph_upload(g.row_ptr, g.col, None)
     with pytest.raises(irgl.IrglError) as e:

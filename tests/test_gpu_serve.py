@@ -74,12 +74,60 @@ def test_server_results_match_oracle_and_alone(irgl, graphs):
     server.close()
 
 
+@pytest.mark.parametrize("gang_edges,team", [(20_000, 8), (1, 4), (20_000, 10_000)])
+def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team):
+    """Tasks on graphs with at least gang_edges edges run on the whole grid
+    between the teams' own tasks; every result equals the oracle, in ring
+    order or not, and the kernel ends and relaunches between waves."""
+    print(f"[case] gang_edges={gang_edges} team={team}", flush=True)
+    server = irgl.irgl_batch_open([hg for _, hg, _ in graphs], cfg={"team": team, "gang_edges": gang_edges},
+                                  ring_cap=32, idle_ms=5)
+    rng = np.random.default_rng(gang_edges + team)
+    for wave in range(2):
+        tasks, tickets, stats = [], [], {}
+        t0 = time.time()
+        for i in range(40):
+            gi = int(rng.integers(0, len(graphs)))
+            g, hg, np_g = graphs[gi]
+            src = gg.pick_sources(g, 50, seed=gi)[int(rng.integers(0, 50))]
+            t = irgl.Task(hg, int(rng.integers(0, 2)), src, with_parent=(i % 4 == 0))
+            while True:
+                tk = irgl.irgl_batch_enqueue(server, t)
+                if tk is not None:
+                    break
+                for old in tickets:  # make room: a slot is reused once its task was polled done
+                    if old not in stats:
+                        st = irgl.irgl_batch_poll(server, old)
+                        if st is not None:
+                            stats[old] = st
+                assert time.time() - t0 < 30.0
+            tasks.append((gi, t))
+            tickets.append(tk)
+        stats.update(_wait(irgl, server, [tk for tk in tickets if tk not in stats]))
+        for (gi, t), tk in zip(tasks, tickets):
+            g, hg, np_g = graphs[gi]
+            st = stats[tk]
+            assert st["status"] == 0
+            ref = _ref(t.kind, np_g, t.src)
+            got = irgl.as_u32_numpy(t.out)
+            np.testing.assert_array_equal(got, ref, err_msg=f"graph {gi} kind {t.kind} src {t.src}")
+            if t.kind == 0:
+                assert st["frontier_edges"] == oracle.edges_scanned(np_g[0], ref)
+            if t.parent is not None:
+                rp, col, w = np_g
+                oracle.validate(rp, col, t.src, got, t.parent.cpu().numpy(), None if t.kind == 0 else w)
+        time.sleep(0.05)  # idle: the kernel ends, the next wave relaunches it
+    server.close()
+
+
 def test_ring_full_then_drain_and_idle_relaunch(irgl, graphs):
     g, hg, np_g = graphs[0]
     server = irgl.irgl_batch_open([hg], cfg={"team": 4}, ring_cap=4, idle_ms=5)
     srcs = gg.pick_sources(g, 20, seed=3)
-    tickets, tasks = [], []
+    tasks = []
+    pending = set()
     busy_seen = False
+    t0 = time.time()
     for s in srcs:
         t = irgl.Task(hg, 1, s)
         while True:
@@ -87,11 +135,13 @@ def test_ring_full_then_drain_and_idle_relaunch(irgl, graphs):
             if tk is not None:
                 break
             busy_seen = True
-            for old in tickets:  # make room
-                irgl.irgl_batch_poll(server, old)
-        tickets.append(tk)
+            for old in list(pending):  # make room: finished slots can be reused
+                if irgl.irgl_batch_poll(server, old) is not None:
+                    pending.discard(old)
+            assert time.time() - t0 < 30.0
+        pending.add(tk)
         tasks.append(t)
-    _wait(irgl, server, tickets)
+    _wait(irgl, server, sorted(pending))
     time.sleep(0.1)  # the server kernel ends after idle_ms without work
     t = irgl.Task(hg, 0, srcs[0])
     tk = irgl.irgl_batch_enqueue(server, t)
