@@ -175,6 +175,9 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--serve-lambda", type=float, default=0.8)
+    ap.add_argument("--calibrate-mb", type=int, default=0,
+                    help="first copy this many MiB device to device once (a copy of known traffic that "
+                         "scales hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,6 +191,14 @@ def main() -> int:
     from paper_1607_05707_amd.workloads import make_workload
 
     dev = torch.device("cuda:0")
+    if args.calibrate_mb > 0:
+        a = torch.ones(args.calibrate_mb << 18, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_mb} MiB read + {args.calibrate_mb} MiB written")
+        del a, b
     kinds = [{"bfs": 0, "sssp": 1}[k] for k in args.kinds.split(",")]
     t0 = time.perf_counter()
     g = make_workload(args.workload, dev, args.sources)
@@ -258,6 +269,7 @@ def main() -> int:
         if st["status"] != 0:
             raise SystemExit(f"kind {k} failed: {irgl.irgl_status_string(st['status'])}")
 
+    names_k = {0: "bfs", 1: "sssp"}
     per_kind_ms = {k: [] for k in kinds}
     for k, s, a, b in events:
         per_kind_ms[k].append(a.elapsed_time(b))
@@ -280,14 +292,24 @@ def main() -> int:
         }
     dom = max(kinds, key=lambda k: kind_summary[k]["total_ms"])
     ks = kind_summary[dom]
+    kname = f"persistent_kernel<{args.block or 256}, irgl::{['BfsOp', 'SsspOp'][dom]}>"
+    # measured HBM bytes per launch of that kernel (rocprofv3 FETCH_SIZE +
+    # WRITE_SIZE, scaled by a plain copy), only while the HIP sources are the
+    # ones the counters were taken on
+    from paper_1607_05707_amd import profiling
+    rec = profiling.load_traffic(os.path.join(ROOT, "profiles",
+                                              f"traffic_{args.workload}_{names_k[dom]}.json"))
+    traffic = int(rec["traffic_bytes_per_launch"]) if rec and rec.get("kernel") == kname else None
     roofline = {
         "bound": "hbm",
         "achieved": ks["alg_gbs"],
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(ks["alg_gbs"] / PEAK_HBM_GBS, 4),
-        "traffic": None,
-        "kernel": f"persistent_kernel<{['BfsOp', 'SsspOp'][dom]}> (+ its init fill)",
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch",
+        "alg_bytes_per_launch": ks["alg_bytes_per_query"],
+        "kernel": f"{kname} (+ its init fill)",
     }
 
     cpu = None
