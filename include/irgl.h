@@ -195,6 +195,28 @@ irgl_status irgl_wallclock_khz(int32_t *khz);
  * n <= 0, m < 0, m >= 2^31), NO_DEVICE, DEVICE. */
 irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out);
 
+/* Degree-sorted relabelling.  A graph uploaded this way is traversed in a
+ * copy whose vertex ids are sorted by decreasing out-degree (ties by id):
+ * most edges of a skewed graph point at few high-degree vertices, whose
+ * levels / distances then share few cache lines and stay in the L2, so most
+ * per-edge probes of a traversal hit L2 instead of the Infinity Cache.
+ * Queries on the handle take and return CALLER vertex ids (sources, levels,
+ * distances, parents; SSSP parents are the smallest caller-id tight
+ * predecessor, as for a plain upload); irgl_bfs / irgl_sssp then need a
+ * larger workspace (irgl_workspace_bytes accounts for it) and end with one
+ * scatter to caller ids.  Batched and served tasks on the handle traverse the
+ * caller's arrays.
+ *
+ * irgl_reorder_bytes: device bytes of the copy (and of its build scratch)
+ * for a graph of n vertices and m edges, weighted or not.
+ * irgl_graph_upload_reordered: checks csr as irgl_graph_upload does (flags
+ * as there), builds the copy in `store` (DEVICE, at least
+ * irgl_reorder_bytes, borrowed until irgl_graph_free, like the CSR arrays,
+ * which also stay borrowed) on the current device's null stream, and
+ * synchronizes.  IRGL_ERR_WORKSPACE_TOO_SMALL when store_bytes is short. */
+irgl_status irgl_reorder_bytes(int32_t n, int64_t m, int32_t weighted, size_t *bytes);
+irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t store_bytes, irgl_graph *out);
+
 /* Release a handle (not the arrays it borrows).  NULL is accepted. */
 irgl_status irgl_graph_free(irgl_graph g);
 

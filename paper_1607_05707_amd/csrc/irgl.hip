@@ -6,6 +6,7 @@
 // resident), and launches either the outlined persistent loop (one
 // cooperative launch per query) or the un-outlined host loop.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstddef>
@@ -57,12 +58,19 @@ struct irgl_server_s {
 struct irgl_graph_s {
     int32_t n;
     int64_t m;
-    const int32_t *row_ptr;
+    const int32_t *row_ptr;   // the arrays single queries traverse (relabelled copy, if any)
     const int32_t *col;
     const uint32_t *w;
     uint32_t flags;
     int device;
     uint64_t weight_sum;  // from IRGL_VALIDATE, else 0
+    // caller's arrays (batched and served tasks traverse these)
+    const int32_t *orig_row_ptr;
+    const int32_t *orig_col;
+    const uint32_t *orig_w;
+    // degree-sorted relabelling (irgl_graph_upload_reordered), else null / empty
+    const int32_t *perm;           // device: internal id -> caller id
+    std::vector<int32_t> inv_host;  // host: caller id -> internal id
 };
 
 namespace {
@@ -190,11 +198,11 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, frontier, hub_v, hub_base, total;
+    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, frontier, hub_v, hub_base, rval, rparent, total;
     uint32_t hub_cap;
 };
 
-Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
+Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     Layout L;
     L.ctrl = 0;
     L.wl0 = align_up(sizeof(Ctrl));
@@ -216,7 +224,10 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c) {
                     ? static_cast<uint32_t>(std::min<int64_t>(g->n, g->m / c.t_grid + 1))
                     : 0u;
     L.hub_base = L.hub_v + align_up(static_cast<size_t>(L.hub_cap) * 4);
-    L.total = L.hub_base + align_up(static_cast<size_t>(L.hub_cap) * 4);
+    // relabelled graph: values and parents under internal ids, scattered at the end
+    L.rval = L.hub_base + align_up(static_cast<size_t>(L.hub_cap) * 4);
+    L.rparent = L.rval + (g->perm ? nb : 0);
+    L.total = L.rparent + (g->perm && with_parent ? nb : 0);
     return L;
 }
 
@@ -362,7 +373,7 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     Cfg c;
     irgl_status st = resolve(g, kind, cfg, &c);
     if (st) return st;
-    const Layout L = layout(g, kind, c);
+    const Layout L = layout(g, kind, c, parent != nullptr);
     if (ws_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
     // SSSP safety cap also covers the threshold-raise invocations (at most one
     // per vertex moved from the far list)
@@ -379,8 +390,9 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.row_ptr = g->row_ptr;
     p.col = g->col;
     p.w = g->w;
-    p.val = out;
-    p.parent = parent;
+    p.val = g->perm ? reinterpret_cast<uint32_t *>(base + L.rval) : out;
+    p.parent = g->perm && parent ? reinterpret_cast<int32_t *>(base + L.rparent) : parent;
+    p.perm = g->perm;
     p.ctrl = reinterpret_cast<Ctrl *>(base + L.ctrl);
     p.wl0 = reinterpret_cast<int32_t *>(base + L.wl0);
     p.wl1 = reinterpret_cast<int32_t *>(base + L.wl1);
@@ -413,10 +425,16 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.max_iter = c.max_iter;
     p.t_wave = c.t_wave;
     p.t_block = c.t_block;
-    p.src = src;
+    p.src = g->perm ? g->inv_host[static_cast<size_t>(src)] : src;
+    p.src_orig = src;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (kind == IRGL_KIND_BFS) st = dispatch_block<BfsOp>(g, p, c, s, kind);
     else st = dispatch_block<SsspOp>(g, p, c, s, kind);
+    if (st == IRGL_OK && g->perm) {
+        hipLaunchKernelGGL(scatter_results_kernel, dim3(fill_grid(g->n, 256)), dim3(256), 0, s, g->n, g->perm,
+                           p.val, p.parent, out, parent);
+        if (hipGetLastError() != hipSuccess) st = hip_fail(hipGetLastError());
+    }
     if (cur != g->device) (void)hipSetDevice(cur);
     return st;
 }
@@ -594,9 +612,9 @@ uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta);
 void fill_desc(TaskDesc &d, const irgl_task &t, Stats *stats, uint32_t delta_override, bool gang = false) {
     std::memset(&d, 0, sizeof(d));
     d.gang = gang ? 1u : 0u;
-    d.row_ptr = t.g->row_ptr;
-    d.col = t.g->col;
-    d.w = t.g->w;
+    d.row_ptr = t.g->orig_row_ptr;
+    d.col = t.g->orig_col;
+    d.w = t.g->orig_w;
     d.out = t.out;
     d.parent = t.parent;
     d.stats = stats;
@@ -667,6 +685,73 @@ __global__ void clear_flag_kernel() {
     g_weight_sum = 0ull;
 }
 
+// ---------------------------------------------------------------------------
+// Degree-sorted relabelling (upload time).  Internal id i is the caller
+// vertex perm[i], in decreasing out-degree order (ties by caller id): the
+// values of the vertices most edges point at then share a few cache lines
+// and stay in L2, so most per-edge probes of a traversal hit L2.
+// ---------------------------------------------------------------------------
+__global__ void degree_keys_kernel(int32_t n, const int32_t *rp, uint32_t *keys, int32_t *ids) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        keys[v] = static_cast<uint32_t>(rp[v + 1] - rp[v]);
+        ids[v] = v;
+    }
+}
+
+__global__ void inverse_kernel(int32_t n, const int32_t *perm, int32_t *inv, int32_t *nrp) {
+    const int32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) nrp[0] = 0;
+    for (int32_t i = i0; i < n; i += gridDim.x * blockDim.x) inv[perm[i]] = i;
+}
+
+// One wavefront per internal vertex copies its range with relabelled targets.
+__global__ void relabel_edges_kernel(int32_t n, const int32_t *perm, const int32_t *inv, const int32_t *rp,
+                                     const int32_t *col, const uint32_t *w, const int32_t *nrp, int32_t *ncol,
+                                     uint32_t *nw) {
+    const int lane = threadIdx.x % kWave;
+    const int32_t waves = static_cast<int32_t>(gridDim.x * (blockDim.x / kWave));
+    for (int32_t u = static_cast<int32_t>(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave); u < n;
+         u += waves) {
+        const int32_t o = perm[u];
+        const int32_t r0 = rp[o], d = rp[o + 1] - r0, dst = nrp[u];
+        for (int32_t k = lane; k < d; k += kWave) {
+            ncol[dst + k] = inv[col[r0 + k]];
+            if (w) nw[dst + k] = w[r0 + k];
+        }
+    }
+}
+
+// Store of a relabelled copy: row offsets, targets, weights, perm, then the
+// build's scratch (sort keys, ids, inverse, library sort/scan scratch).
+struct ReorderLayout {
+    size_t nrp, ncol, nw, perm, keys_in, keys_out, ids_in, inv, tmp, tmp_bytes, total;
+};
+
+irgl_status reorder_layout(int32_t n, int64_t m, bool weighted, ReorderLayout *out) {
+    ReorderLayout L;
+    const size_t nb = align_up(static_cast<size_t>(n) * 4);
+    L.nrp = 0;
+    L.ncol = align_up(static_cast<size_t>(n + 1) * 4);
+    L.nw = L.ncol + align_up(static_cast<size_t>(m) * 4 + 4);
+    L.perm = L.nw + (weighted ? align_up(static_cast<size_t>(m) * 4 + 4) : 0);
+    L.keys_in = L.perm + nb;
+    L.keys_out = L.keys_in + nb;
+    L.ids_in = L.keys_out + nb;
+    L.inv = L.ids_in + nb;
+    L.tmp = L.inv + nb;
+    size_t sort_b = 0, scan_b = 0;
+    IRGL_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_b, static_cast<const uint32_t *>(nullptr),
+                                                          static_cast<uint32_t *>(nullptr),
+                                                          static_cast<const int32_t *>(nullptr),
+                                                          static_cast<int32_t *>(nullptr), n));
+    IRGL_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, scan_b, static_cast<const uint32_t *>(nullptr),
+                                              static_cast<int32_t *>(nullptr), n));
+    L.tmp_bytes = align_up(std::max(sort_b, scan_b));
+    L.total = L.tmp + L.tmp_bytes;
+    *out = L;
+    return IRGL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -712,9 +797,9 @@ irgl_status irgl_wallclock_khz(int32_t *khz) {
     return IRGL_OK;
 }
 
-irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
-    if (!csr || !out) return IRGL_ERR_INVALID_ARGUMENT;
-    *out = nullptr;
+// Argument checks, the device, and (IRGL_VALIDATE) the on-device CSR check
+// and weight sum; shared by both uploads.
+static irgl_status upload_prologue(const irgl_csr *csr, int *dev_out, unsigned long long *wsum_out) {
     if (csr->n <= 0 || csr->m < 0 || csr->m >= (int64_t(1) << 31)) return IRGL_ERR_INVALID_ARGUMENT;
     if (!csr->row_ptr || (csr->m > 0 && !csr->col)) return IRGL_ERR_INVALID_ARGUMENT;
     int count = 0;
@@ -724,6 +809,7 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     }
     int dev = 0;
     IRGL_HIP(hipGetDevice(&dev));
+    *dev_out = dev;
     unsigned long long weight_sum = 0;
     if (csr->flags & IRGL_VALIDATE) {
         hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, 0);
@@ -741,6 +827,17 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
         if (bad) return IRGL_ERR_INVALID_GRAPH;
         IRGL_HIP(hipMemcpy(&weight_sum, wsum, 8, hipMemcpyDeviceToHost));
     }
+    *wsum_out = csr->w ? weight_sum : 0ull;
+    return IRGL_OK;
+}
+
+irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
+    if (!csr || !out) return IRGL_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int dev = 0;
+    unsigned long long weight_sum = 0;
+    irgl_status st = upload_prologue(csr, &dev, &weight_sum);
+    if (st) return st;
     irgl_graph_s *g = new (std::nothrow) irgl_graph_s;
     if (!g) return IRGL_ERR_INVALID_ARGUMENT;
     g->n = csr->n;
@@ -751,6 +848,79 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     g->flags = csr->flags;
     g->device = dev;
     g->weight_sum = csr->w ? weight_sum : 0;
+    g->orig_row_ptr = csr->row_ptr;
+    g->orig_col = csr->col;
+    g->orig_w = csr->w;
+    g->perm = nullptr;
+    *out = g;
+    return IRGL_OK;
+}
+
+irgl_status irgl_reorder_bytes(int32_t n, int64_t m, int32_t weighted, size_t *bytes) {
+    if (!bytes || n <= 0 || m < 0 || m >= (int64_t(1) << 31)) return IRGL_ERR_INVALID_ARGUMENT;
+    ReorderLayout L;
+    irgl_status st = reorder_layout(n, m, weighted != 0, &L);
+    if (st) return st;
+    *bytes = L.total;
+    return IRGL_OK;
+}
+
+irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t store_bytes, irgl_graph *out) {
+    if (!csr || !out || !store) return IRGL_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    int dev = 0;
+    unsigned long long weight_sum = 0;
+    irgl_status st = upload_prologue(csr, &dev, &weight_sum);
+    if (st) return st;
+    const int32_t n = csr->n;
+    const int64_t m = csr->m;
+    ReorderLayout L;
+    st = reorder_layout(n, m, csr->w != nullptr, &L);
+    if (st) return st;
+    if (store_bytes < L.total) return IRGL_ERR_WORKSPACE_TOO_SMALL;
+    char *b = static_cast<char *>(store);
+    int32_t *nrp = reinterpret_cast<int32_t *>(b + L.nrp);
+    int32_t *ncol = reinterpret_cast<int32_t *>(b + L.ncol);
+    uint32_t *nw = csr->w ? reinterpret_cast<uint32_t *>(b + L.nw) : nullptr;
+    int32_t *perm = reinterpret_cast<int32_t *>(b + L.perm);
+    uint32_t *keys_in = reinterpret_cast<uint32_t *>(b + L.keys_in);
+    uint32_t *keys_out = reinterpret_cast<uint32_t *>(b + L.keys_out);
+    int32_t *ids_in = reinterpret_cast<int32_t *>(b + L.ids_in);
+    int32_t *inv = reinterpret_cast<int32_t *>(b + L.inv);
+    void *tmp = b + L.tmp;
+    const int grid = fill_grid(static_cast<uint32_t>(n), 256);
+    hipLaunchKernelGGL(degree_keys_kernel, dim3(grid), dim3(256), 0, 0, n, csr->row_ptr, keys_in, ids_in);
+    IRGL_HIP(hipGetLastError());
+    size_t tb = L.tmp_bytes;
+    IRGL_HIP(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, keys_in, keys_out, ids_in, perm, n));
+    tb = L.tmp_bytes;
+    IRGL_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tb, keys_out, nrp + 1, n));
+    hipLaunchKernelGGL(inverse_kernel, dim3(grid), dim3(256), 0, 0, n, perm, inv, nrp);
+    IRGL_HIP(hipGetLastError());
+    const int egrid = std::max(1, std::min(4096, (n + 3) / 4));  // 4 wavefronts per workgroup
+    hipLaunchKernelGGL(relabel_edges_kernel, dim3(egrid), dim3(256), 0, 0, n, perm, inv, csr->row_ptr, csr->col,
+                       csr->w, nrp, ncol, nw);
+    IRGL_HIP(hipGetLastError());
+    irgl_graph_s *g = new (std::nothrow) irgl_graph_s;
+    if (!g) return IRGL_ERR_INVALID_ARGUMENT;
+    g->inv_host.resize(static_cast<size_t>(n));
+    const hipError_t e = hipMemcpy(g->inv_host.data(), inv, static_cast<size_t>(n) * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e);
+    }
+    g->n = n;
+    g->m = m;
+    g->row_ptr = nrp;
+    g->col = ncol;
+    g->w = nw;
+    g->flags = csr->flags;
+    g->device = dev;
+    g->weight_sum = weight_sum;
+    g->orig_row_ptr = csr->row_ptr;
+    g->orig_col = csr->col;
+    g->orig_w = csr->w;
+    g->perm = perm;
     *out = g;
     return IRGL_OK;
 }
@@ -762,13 +932,12 @@ irgl_status irgl_graph_free(irgl_graph g) {
 
 irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent,
                                  const irgl_config *cfg, size_t *bytes) {
-    (void)with_parent;
     if (!g || !bytes) return IRGL_ERR_INVALID_ARGUMENT;
     if (kind != IRGL_KIND_BFS && kind != IRGL_KIND_SSSP) return IRGL_ERR_INVALID_ARGUMENT;
     Cfg c;
     irgl_status st = resolve(g, kind, cfg, &c);
     if (st) return st;
-    *bytes = layout(g, kind, c).total;
+    *bytes = layout(g, kind, c, with_parent != 0).total;
     return IRGL_OK;
 }
 

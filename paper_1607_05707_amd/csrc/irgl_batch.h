@@ -81,6 +81,8 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.t_block = bp.t_block;
     p.t_grid = bp.t_grid;
     p.src = t.src;
+    p.src_orig = t.src;
+    p.perm = nullptr;  // batched tasks run on the caller's labelling
     p.it = 0;
     p.wd_ticks = bp.wd_ticks;
     p.barrier = bp.barrier;
@@ -139,7 +141,7 @@ __device__ __forceinline__ bool run_task(const BatchParams &bp, const TaskDesc &
         Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{nullptr, nullptr, 0u, ctrl, nullptr},
                    Sink{nullptr, nullptr, 0u, ctrl, nullptr}, kInf};
         unsigned long long pe = 0;
-        const SsspParentOp op{p.val, p.w, p.parent, p.src};
+        const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
         expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr,
                                 p.col, op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, pe,
                                 tm);

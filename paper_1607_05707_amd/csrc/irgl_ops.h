@@ -51,6 +51,8 @@ struct Params {
     int32_t t_block;
     int32_t t_grid;       // 0 disables the grid tier
     int32_t src;
+    int32_t src_orig;     // the source's caller id (parents are caller ids)
+    const int32_t *perm;  // relabelled graph: internal id -> caller id, else null
     uint32_t it;          // host-loop mode: the invocation to run
     unsigned long long wd_ticks;
     uint32_t barrier;  // grid-barrier coherence scheme (kBar*)
@@ -85,6 +87,7 @@ struct BfsOp {
     int32_t *parent;
     const uint32_t *visited;  // bitmap: a set bit means "visited" (never a false positive)
     uint32_t next;            // label of vertices found in this invocation
+    const int32_t *perm;      // relabelled graph: parents are stored as caller ids
     __device__ __forceinline__ uint32_t vertex_value(int) const { return 0u; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&)[kU], const int (&d)[kU], const int (&sv)[kU],
@@ -112,7 +115,7 @@ struct BfsOp {
         if (parent) {
 #pragma unroll
             for (int k = 0; k < kU; ++k)
-                if (act[k]) parent[d[k]] = sv[k];
+                if (act[k]) parent[d[k]] = perm ? perm[sv[k]] : sv[k];
         }
     }
 };
@@ -195,6 +198,7 @@ struct SsspParentOp {
     const uint32_t *w;
     int32_t *parent;
     int32_t src;
+    const int32_t *perm;  // relabelled graph: the smallest CALLER id wins, stored as a caller id
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t dv) const { return dv != kInf; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&sv)[kU],
@@ -208,7 +212,8 @@ struct SsspParentOp {
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             if (act[k] && d[k] != src && s[k] == cur[k] && s[k] >= dv[k])
-                atomicMin(reinterpret_cast<uint32_t *>(&parent[d[k]]), static_cast<uint32_t>(sv[k]));
+                atomicMin(reinterpret_cast<uint32_t *>(&parent[d[k]]),
+                          static_cast<uint32_t>(perm ? perm[sv[k]] : sv[k]));
             act[k] = false;
         }
     }

@@ -18,7 +18,7 @@ __device__ __forceinline__ void init_arrays(const Params &p, int with_stamp, Tea
     for (uint32_t i = tm.id * blockDim.x + threadIdx.x; i < n; i += tm.size * blockDim.x) {
         const bool s = static_cast<int>(i) == p.src;
         p.val[i] = s ? 0u : kInf;
-        if (p.parent) p.parent[i] = s ? p.src : -1;
+        if (p.parent) p.parent[i] = s ? p.src_orig : -1;
         if (with_stamp) {
             p.stamp[i] = kInf;
             p.far_flag[i] = 0u;
@@ -72,7 +72,7 @@ __device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, 
 
 template <>
 __device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it, uint32_t) {
-    return BfsOp{p.val, p.parent, p.visited, it + 1};
+    return BfsOp{p.val, p.parent, p.visited, it + 1, p.perm};
 }
 
 // Refresh a vertex bitmap from the value array: bit v = (val[v] < below).
@@ -222,7 +222,7 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
         }
         if (found >= 0) {
             p.val[v] = next;
-            if (p.parent) p.parent[v] = found;
+            if (p.parent) p.parent[v] = p.perm ? p.perm[found] : found;
             pu.mf += static_cast<unsigned long long>(r1 - r0);
         }
         pu.near(found >= 0, static_cast<int>(v));
@@ -514,10 +514,21 @@ __global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{nullptr, nullptr, 0u, p.ctrl, nullptr},
                Sink{nullptr, nullptr, 0u, p.ctrl, nullptr}, kInf};
     unsigned long long edges = 0;
-    const SsspParentOp op{p.val, p.w, p.parent, p.src};
+    const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
     expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr, p.col,
                             op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, edges,
                             whole_grid());
+}
+
+// Relabelled graph: results computed under internal ids (vals, parents
+// already caller ids) go to the caller's arrays under caller ids.
+__global__ void scatter_results_kernel(int32_t n, const int32_t *perm, const uint32_t *val, const int32_t *par,
+                                       uint32_t *out, int32_t *out_parent) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t o = perm[v];
+        out[o] = val[v];
+        if (out_parent) out_parent[o] = par[v];
+    }
 }
 
 // On-device CSR validation: row_ptr[0] == 0, monotone, row_ptr[n] == m,

@@ -93,6 +93,10 @@ _lib.irgl_last_hip_error.restype = ctypes.c_int32
 _lib.irgl_last_hip_error.argtypes = []
 _lib.irgl_graph_upload.restype = ctypes.c_int32
 _lib.irgl_graph_upload.argtypes = [ctypes.POINTER(irgl_csr), ctypes.POINTER(_c)]
+_lib.irgl_reorder_bytes.restype = ctypes.c_int32
+_lib.irgl_reorder_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_graph_upload_reordered.restype = ctypes.c_int32
+_lib.irgl_graph_upload_reordered.argtypes = [ctypes.POINTER(irgl_csr), _c, ctypes.c_size_t, ctypes.POINTER(_c)]
 _lib.irgl_graph_free.restype = ctypes.c_int32
 _lib.irgl_graph_free.argtypes = [_c]
 _lib.irgl_workspace_bytes.restype = ctypes.c_int32
@@ -188,7 +192,7 @@ class Graph:
 
     Holds references to the borrowed tensors for the handle's lifetime."""
 
-    def __init__(self, handle: int, n: int, m: int, row_ptr, col, w, flags: int):
+    def __init__(self, handle: int, n: int, m: int, row_ptr, col, w, flags: int, store=None):
         self.handle = handle
         self.n = n
         self.m = m
@@ -196,6 +200,11 @@ class Graph:
         self.col = col
         self.w = w
         self.flags = flags
+        self.store = store  # device store of a relabelled copy (irgl_graph_upload_reordered)
+
+    @property
+    def reordered(self) -> bool:
+        return self.store is not None
 
     @property
     def weighted(self) -> bool:
@@ -228,6 +237,33 @@ def irgl_graph_upload(row_ptr: torch.Tensor, col: torch.Tensor, w: Optional[torc
     h = ctypes.c_void_p()
     _check(_lib.irgl_graph_upload(ctypes.byref(csr), ctypes.byref(h)), "irgl_graph_upload")
     return Graph(h.value, n, m, row_ptr, col, w, flags)
+
+
+def irgl_reorder_bytes(n: int, m: int, weighted: bool) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.irgl_reorder_bytes(int(n), int(m), int(bool(weighted)), ctypes.byref(out)), "irgl_reorder_bytes")
+    return int(out.value)
+
+
+def irgl_graph_upload_reordered(row_ptr: torch.Tensor, col: torch.Tensor, w: Optional[torch.Tensor] = None,
+                                flags: int = 0, store: Optional[torch.Tensor] = None) -> Graph:
+    """Register a device CSR traversed in a degree-sorted relabelled copy built
+    in `store` (allocated here when not given); ids stay the caller's."""
+    n = int(row_ptr.numel()) - 1
+    m = int(col.numel())
+    if store is None:
+        store = torch.empty(irgl_reorder_bytes(n, m, w is not None), dtype=torch.uint8, device=row_ptr.device)
+    csr = irgl_csr()
+    csr.n = n
+    csr.m = m
+    csr.row_ptr = _dev_ptr(row_ptr, "row_ptr", _I32)
+    csr.col = _dev_ptr(col, "col", _I32) if m > 0 else None
+    csr.w = _dev_ptr(w, "w", _I32, m) if w is not None else None
+    csr.flags = int(flags)
+    h = ctypes.c_void_p()
+    _check(_lib.irgl_graph_upload_reordered(ctypes.byref(csr), _dev_ptr(store, "store", (torch.uint8,)),
+                                            store.numel(), ctypes.byref(h)), "irgl_graph_upload_reordered")
+    return Graph(h.value, n, m, row_ptr, col, w, flags, store=store)
 
 
 def irgl_graph_free(g: Graph) -> None:
@@ -322,9 +358,12 @@ def query(g: Graph, kind: int, src: int, with_parent: bool = False, cfg=None, st
     return out, parent, st
 
 
-def upload(g, flags: int = IRGL_VALIDATE) -> Graph:
-    """Register a graphgen.CSRGraph whose tensors are already on the device."""
+def upload(g, flags: int = IRGL_VALIDATE, reorder: bool = False) -> Graph:
+    """Register a graphgen.CSRGraph whose tensors are already on the device
+    (reorder: traverse a degree-sorted relabelled copy)."""
     fl = flags | (IRGL_SYMMETRIC if getattr(g, "symmetric", False) else 0)
+    if reorder:
+        return irgl_graph_upload_reordered(g.row_ptr, g.col, g.w, fl)
     return irgl_graph_upload(g.row_ptr, g.col, g.w, fl)
 
 

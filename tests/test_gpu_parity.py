@@ -190,6 +190,42 @@ def test_barrier_schemes(irgl, barrier):
     _check_query(irgl, r, hr, BFS, r.sources[2], {"barrier": barrier, "grid": 37})
 
 
+def test_reordered_upload(irgl):
+    """Degree-sorted relabelling: the same levels and distances under caller
+    ids, valid parents, and SSSP parents identical to the plain upload's
+    (smallest caller-id tight predecessor), in every launch form."""
+    g = _dev(gg.rmat(14, seed=51, weight_seed=52, wmax=255))
+    hr = irgl.upload(g, reorder=True)
+    hp = irgl.upload(g)
+    assert hr.reordered
+    for src in gg.pick_sources(g, 3, seed=53):
+        for cfg in (None, {"mode": 1}, {"delta": 16}, {"block": 512, "do_alpha": 1, "do_beta": 1},
+                    {"t_bitmap": 0xFFFFFFFF, "t_grid": -1}):
+            _check_query(irgl, g, hr, BFS, src, cfg)
+            _check_query(irgl, g, hr, SSSP, src, cfg)
+        _, p1, _ = irgl.query(hr, SSSP, src, with_parent=True)
+        _, p2, _ = irgl.query(hp, SSSP, src, with_parent=True)
+        assert torch.equal(p1, p2)
+        # a batch on the relabelled handle traverses the caller's arrays
+        t = irgl.Task(hr, SSSP, src)
+        b = irgl.irgl_batch_submit([t], cfg={"team": 8})
+        irgl.irgl_batch_wait(b)
+        assert torch.equal(t.out, irgl.query(hp, SSSP, src)[0])
+    d = _dev(gg.random_directed(3000, 30000, seed=61, weight_seed=62))
+    hd = irgl.upload(d, reorder=True)
+    for src in (0, 1, 2999):
+        _check_query(irgl, d, hd, BFS, src)
+        _check_query(irgl, d, hd, SSSP, src)
+    one = _dev(gg.from_edges(1, [], [], [], name="single"))
+    h1 = irgl.upload(one, reorder=True)
+    _check_query(irgl, one, h1, BFS, 0)
+    nb = irgl.irgl_reorder_bytes(g.n, g.m, True)
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.irgl_graph_upload_reordered(g.row_ptr, g.col, g.w, 0,
+                                         store=torch.empty(nb - 1, dtype=torch.uint8, device=g.row_ptr.device))
+    assert e.value.status == irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
+
+
 def test_road_grid_small(irgl):
     g = _dev(gg.config_road(width=256))
     hg = irgl.upload(g)
