@@ -168,6 +168,8 @@ def main() -> int:
     ap.add_argument("--t-bitmap", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--mode", default="persistent", choices=["persistent", "hostloop"])
+    ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
+                    help="1: upload through irgl_graph_upload_reordered (degree-sorted relabelling)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -204,7 +206,7 @@ def main() -> int:
     g = make_workload(args.workload, dev, args.sources)
     torch.cuda.synchronize()
     log(f"generated {g.name}: n={g.n} m={g.m} sources={len(g.sources)} in {time.perf_counter() - t0:.1f}s")
-    hg = irgl.upload(g)
+    hg = irgl.upload(g, reorder=bool(args.reorder))
     cfg = {"block": args.block, "t_wave": args.t_wave, "t_block": args.t_block, "t_grid": args.t_grid,
            "t_bitmap": args.t_bitmap, "grid": args.grid,
            "mode": 1 if args.mode == "hostloop" else 0}
@@ -347,6 +349,7 @@ def main() -> int:
             "queries_per_step": len(sources) * len(kinds),
             "mode": args.mode,
             "block": args.block or "default",
+            "upload": "degree-sorted relabelling" if args.reorder else "caller ids",
         },
         "per_kind": {names[k]: {kk: vv for kk, vv in kind_summary[k].items() if kk != "total_ms"}
                      for k in kinds},

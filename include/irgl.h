@@ -74,7 +74,6 @@ enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
 #define IRGL_DO_OFF 0xFFFFFFFFu
 #define IRGL_BARRIER_XCD 0u
 #define IRGL_BARRIER_WORKGROUP 1u
-#define IRGL_BARRIER_XCD_INV 2u
 
 /* Launch modes. */
 enum {
@@ -155,10 +154,9 @@ typedef struct irgl_config {
                              mode), vertices deferred to the grid tier; then the end
                              tick at 4 x iterations */
     uint32_t barrier;     /* grid-barrier coherence scheme: IRGL_BARRIER_XCD (default:
-                             one L2 write-back per XCD per barrier),
+                             one L2 write-back per XCD per barrier) or
                              IRGL_BARRIER_WORKGROUP (write-back and invalidate per
-                             workgroup) or IRGL_BARRIER_XCD_INV (also one L2
-                             invalidate per XCD).  The XCD schemes fall back to
+                             workgroup).  IRGL_BARRIER_XCD falls back to
                              IRGL_BARRIER_WORKGROUP for a launch whose workgroups are
                              not dealt round-robin to the XCDs.  Results do not
                              depend on it. */

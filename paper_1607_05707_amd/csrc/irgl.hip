@@ -89,9 +89,7 @@ irgl_status hip_fail(hipError_t e) {
         if (e_ != hipSuccess) return hip_fail(e_);       \
     } while (0)
 
-static_assert(kBarXcd == IRGL_BARRIER_XCD && kBarWorkgroup == IRGL_BARRIER_WORKGROUP &&
-                  kBarXcdInv == IRGL_BARRIER_XCD_INV,
-              "barrier scheme values");
+static_assert(kBarXcd == IRGL_BARRIER_XCD && kBarWorkgroup == IRGL_BARRIER_WORKGROUP, "barrier scheme values");
 constexpr size_t kAlign = 256;
 
 // Default bitmap refresh point: a refresh scans all n vertices, so it pays
@@ -192,7 +190,7 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
     // SSSP near/far step: explicit, or derived from the graph's shape
     r.delta = (c && c->delta) ? c->delta : default_delta(g);
     r.barrier = c ? c->barrier : IRGL_BARRIER_XCD;
-    if (r.barrier > IRGL_BARRIER_XCD_INV) return IRGL_ERR_CONFIG;
+    if (r.barrier > IRGL_BARRIER_WORKGROUP) return IRGL_ERR_CONFIG;
     *out = r;
     return IRGL_OK;
 }
@@ -479,7 +477,7 @@ irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
     r.barrier = c ? c->barrier : IRGL_BARRIER_XCD;
-    if (r.barrier > IRGL_BARRIER_XCD_INV) return IRGL_ERR_CONFIG;
+    if (r.barrier > IRGL_BARRIER_WORKGROUP) return IRGL_ERR_CONFIG;
     r.gang_edges = (c && c->gang_edges) ? c->gang_edges : kDefaultGangEdges;
     *out = r;
     return IRGL_OK;

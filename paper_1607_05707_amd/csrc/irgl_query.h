@@ -54,6 +54,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
         c->mf[0] = static_cast<unsigned long long>(p.row_ptr[p.src + 1] - p.row_ptr[p.src]);
         c->mf[1] = 0;
         c->mf[2] = 0;
+        c->bu_scan = 0;
         p.wl0[0] = p.src;
 }
 
@@ -254,9 +255,11 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, {}, {}, kInf};
     LoopResult r{0u, 0ull, 0ull, 0u, 0ull};
     // BFS direction choice (needs the frontier bitmap; symmetric graphs only)
-    const bool can_pull = !Op::kFar && p.frontier != nullptr;
+    bool can_pull = !Op::kFar && p.frontier != nullptr;
     bool pull = false;
     unsigned long long m_seen = 0;  // out-degree sum of all worklists so far
+    unsigned long long m_f = 0;     // out-degree sum of this invocation's worklist
+    unsigned long long bu_seen = 0; // ctrl->bu_scan after the last bottom-up invocation
     if (can_pull) pu.deg_rp = p.row_ptr;
     const int32_t *in = p.wl0;
     int32_t *out = p.wl1;
@@ -316,8 +319,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             ++tr;
         } else if (can_pull && ([&] {
                        // uniform: the settled out-degree sum of this worklist
-                       const unsigned long long m_f = __hip_atomic_load(&ctrl->mf[it % 3], __ATOMIC_RELAXED,
-                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                       m_f = __hip_atomic_load(&ctrl->mf[it % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                        m_seen += m_f;
                        const long long m_u = p.m - static_cast<long long>(m_seen);
                        if (!pull) pull = static_cast<long long>(m_f) * p.do_alpha > m_u;
@@ -334,7 +336,18 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             pull_level<B>(p, it + 1, tm, pu, r.edges);
             refreshed = r.items;  // the visited bitmap was rebuilt for this invocation
             drain_all<B, Op>(pu, sm);
+            add_block_total<B>(r.edges - edges_before, &ctrl->bu_scan);
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            // uniform: a bottom-up invocation that scanned more edges than the
+            // top-down one would have (a high-diameter graph, where unvisited
+            // vertices rarely touch the frontier) ends bottom-up for the query
+            const unsigned long long bu_now =
+                __hip_atomic_load(&ctrl->bu_scan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (bu_now - bu_seen > m_f) {
+                can_pull = false;
+                pull = false;
+            }
+            bu_seen = bu_now;
             if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
         } else {
             pu.skf = far_sink(p, tr);

@@ -49,7 +49,6 @@ IRGL_DELTA_NONE = 0xFFFFFFFF
 IRGL_DO_OFF = 0xFFFFFFFF
 IRGL_BARRIER_XCD = 0
 IRGL_BARRIER_WORKGROUP = 1
-IRGL_BARRIER_XCD_INV = 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "

@@ -53,7 +53,7 @@ def _make_tasks(irgl, graphs, per_graph, with_parent, seed):
 
 
 @pytest.mark.parametrize("team,block,barrier", [(16, 256, 0), (1, 256, 0), (4, 512, 0), (10_000, 256, 0),
-                                                (16, 256, 1), (16, 256, 2), (3, 256, 2), (10_000, 256, 2)])
+                                                (16, 256, 1), (3, 256, 0), (10_000, 256, 1)])
 def test_batch_matches_oracle(irgl, graphs, team, block, barrier):
     tasks, meta = _make_tasks(irgl, graphs, per_graph=5, with_parent=(team == 16), seed=team)
     print(f"[case] batch team={team} block={block} barrier={barrier} tasks={len(tasks)}", flush=True)
