@@ -229,13 +229,31 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     return L;
 }
 
+struct OccEntry {
+    const void *kernel;
+    int block, dev, per_cu;
+};
+std::mutex g_occ_mu;
+std::vector<OccEntry> g_occ;
+
 template <class K>
 irgl_status coresident_grid(K kernel, int block, int dev, int requested, int *grid) {
     DeviceInfo di;
     irgl_status st = device_info(dev, &di);
     if (st) return st;
-    int per_cu = 0;
-    IRGL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+    // the occupancy query costs tens of microseconds: once per kernel, block and device
+    int per_cu = -1;
+    const void *key = reinterpret_cast<const void *>(kernel);
+    {
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        for (const OccEntry &e : g_occ)
+            if (e.kernel == key && e.block == block && e.dev == dev) per_cu = e.per_cu;
+    }
+    if (per_cu < 0) {
+        IRGL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
+        std::lock_guard<std::mutex> lk(g_occ_mu);
+        g_occ.push_back(OccEntry{key, block, dev, per_cu});
+    }
     // Measured on gfx950: a grid that fills 7 waves per SIMD is not fully
     // co-resident (the barrier then waits for workgroups that never start),
     // while 6 waves per SIMD is.  Cap the grid at 6 waves per SIMD.

@@ -338,12 +338,13 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             drain_all<B, Op>(pu, sm);
             add_block_total<B>(r.edges - edges_before, &ctrl->bu_scan);
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
-            // uniform: a bottom-up invocation that scanned more edges than the
-            // top-down one would have (a high-diameter graph, where unvisited
-            // vertices rarely touch the frontier) ends bottom-up for the query
+            // uniform: a bottom-up invocation that scanned more than twice the
+            // edges the top-down one would have (a high-diameter graph, where
+            // unvisited vertices rarely touch the frontier) ends bottom-up for
+            // the query
             const unsigned long long bu_now =
                 __hip_atomic_load(&ctrl->bu_scan, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (bu_now - bu_seen > m_f) {
+            if (bu_now - bu_seen > 2 * m_f) {
                 can_pull = false;
                 pull = false;
             }
