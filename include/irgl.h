@@ -282,6 +282,11 @@ typedef struct irgl_batch_config {
     uint32_t gang_edges; /* open batches: a task on a graph with at least this many
                             edges runs on the whole grid (all teams together, in
                             ring order) instead of one team (0 = 2^23) */
+    uint32_t gang_queue; /* open batches: a task enqueued while fewer than this many
+                            tasks are in flight (issued, not yet polled done) also
+                            runs on the whole grid: at low load the whole grid gives
+                            the lowest latency, at high load teams give throughput
+                            (0 = off) */
 } irgl_batch_config;
 
 typedef struct irgl_batch_s *irgl_batch;

@@ -50,6 +50,8 @@ struct irgl_server_s {
     int64_t small_n, small_m;  // team regions are sized for these (graphs below gang_edges)
     int64_t gang_n, gang_m;    // the gang region is sized for these
     uint32_t gang_edges;
+    uint32_t gang_queue;
+    uint64_t completed;        // tickets polled done
     void *host_mem;          // pinned: ring | tail | stop | done[] | stats[]
     void *params;            // ServerParams (host copy reused for launches)
     uint64_t *acked;         // per ring slot: 1 + the last ticket polled as done
@@ -196,7 +198,8 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, far0, far1, far_flag, visited, frontier, hub_v, hub_base, rval, rparent, total;
+    size_t ctrl, wl0, wl1, stamp, shadow, far0, far1, far_flag, visited, frontier, hub_v, hub_base, rval, rparent,
+        total;
     uint32_t hub_cap;
 };
 
@@ -208,7 +211,8 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     L.stamp = L.wl1 + align_up(static_cast<size_t>(c.cap) * 4);
     const size_t nb = align_up(static_cast<size_t>(g->n) * 4);
     const bool sssp = kind == IRGL_KIND_SSSP;
-    L.far0 = L.stamp + (sssp ? nb : 0);
+    L.shadow = L.stamp + (sssp ? nb : 0);
+    L.far0 = L.shadow + (sssp ? nb : 0);
     L.far1 = L.far0 + (sssp ? nb : 0);
     L.far_flag = L.far1 + (sssp ? nb : 0);
     L.visited = L.far_flag + (sssp ? nb : 0);
@@ -413,6 +417,7 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.wl0 = reinterpret_cast<int32_t *>(base + L.wl0);
     p.wl1 = reinterpret_cast<int32_t *>(base + L.wl1);
     p.stamp = kind == IRGL_KIND_SSSP ? reinterpret_cast<uint32_t *>(base + L.stamp) : nullptr;
+    p.shadow = kind == IRGL_KIND_SSSP ? reinterpret_cast<uint32_t *>(base + L.shadow) : nullptr;
     const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
     p.visited = (c.t_bitmap != IRGL_BITMAP_NEVER || pull) ? reinterpret_cast<uint32_t *>(base + L.visited)
                                                            : nullptr;
@@ -462,7 +467,8 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
 struct BatchLayout {
     size_t queue, team_task, tasks, stats, scratch, total;
     size_t team_bytes;
-    size_t off_wl0, off_wl1, off_stamp, off_far0, off_far1, off_far_flag, off_visited, off_hub_v, off_hub_base;
+    size_t off_wl0, off_wl1, off_stamp, off_shadow, off_far0, off_far1, off_far_flag, off_visited, off_hub_v,
+        off_hub_base;
     uint32_t cap, hub_cap;
     int teams;
     int team;  // workgroups per team
@@ -476,6 +482,7 @@ struct BatchCfg {
     int block, team, t_wave, t_block, t_grid, grid;
     uint32_t delta, watchdog_ms, barrier;
     uint32_t gang_edges;  // server: tasks on graphs with at least this many edges run on the whole grid
+    uint32_t gang_queue;  // server: ... and any task enqueued while fewer than this many are in flight
 };
 
 irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
@@ -497,6 +504,7 @@ irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
     r.barrier = c ? c->barrier : IRGL_BARRIER_XCD;
     if (r.barrier > IRGL_BARRIER_WORKGROUP) return IRGL_ERR_CONFIG;
     r.gang_edges = (c && c->gang_edges) ? c->gang_edges : kDefaultGangEdges;
+    r.gang_queue = c ? c->gang_queue : 0u;
     *out = r;
     return IRGL_OK;
 }
@@ -530,6 +538,7 @@ void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, BatchL
     L->off_wl0 = o;  o += nb;
     L->off_wl1 = o;  o += nb;
     L->off_stamp = o;  o += any_sssp ? nb : 0;
+    L->off_shadow = o;  o += any_sssp ? nb : 0;
     L->off_far0 = o;  o += any_sssp ? nb : 0;
     L->off_far1 = o;  o += any_sssp ? nb : 0;
     L->off_far_flag = o;  o += any_sssp ? nb : 0;
@@ -655,6 +664,7 @@ void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const 
     bp.off_wl0 = L.off_wl0;
     bp.off_wl1 = L.off_wl1;
     bp.off_stamp = L.off_stamp;
+    bp.off_shadow = L.off_shadow;
     bp.off_far0 = L.off_far0;
     bp.off_far1 = L.off_far1;
     bp.off_far_flag = L.off_far_flag;
@@ -1139,10 +1149,12 @@ static irgl_status server_plan(const irgl_graph *graphs, int32_t ngraphs, const 
     for (int32_t i = 0; i < ngraphs; ++i) {
         if (!graphs[i]) return IRGL_ERR_INVALID_ARGUMENT;
         if (graphs[i]->device != graphs[0]->device) return IRGL_ERR_INVALID_ARGUMENT;
-        if (graphs[i]->m >= static_cast<int64_t>(c.gang_edges)) {
+        // with gang_queue any task may run as a gang: the gang region fits every graph
+        if (c.gang_queue > 0 || graphs[i]->m >= static_cast<int64_t>(c.gang_edges)) {
             P.gang_n = std::max<int64_t>(P.gang_n, graphs[i]->n);
             P.gang_m = std::max<int64_t>(P.gang_m, graphs[i]->m);
-        } else {
+        }
+        if (graphs[i]->m < static_cast<int64_t>(c.gang_edges)) {
             P.small_n = std::max<int64_t>(P.small_n, graphs[i]->n);
             P.small_m = std::max<int64_t>(P.small_m, graphs[i]->m);
         }
@@ -1225,6 +1237,7 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sp->gang.off_wl0 = P.G.off_wl0;
     sp->gang.off_wl1 = P.G.off_wl1;
     sp->gang.off_stamp = P.G.off_stamp;
+    sp->gang.off_shadow = P.G.off_shadow;
     sp->gang.off_far0 = P.G.off_far0;
     sp->gang.off_far1 = P.G.off_far1;
     sp->gang.off_far_flag = P.G.off_far_flag;
@@ -1258,6 +1271,8 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sv->gang_n = P.gang_n;
     sv->gang_m = P.gang_m;
     sv->gang_edges = c.gang_edges;
+    sv->gang_queue = c.gang_queue;
+    sv->completed = 0;
     sv->host_mem = hm;
     sv->params = sp;
     if (hipEventCreateWithFlags(&sv->ran, hipEventDisableTiming) != hipSuccess) {
@@ -1322,7 +1337,9 @@ irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *t
     if (st) return st;
     if (task->g->device != s->device) return IRGL_ERR_INVALID_ARGUMENT;
     ServerParams *sp = static_cast<ServerParams *>(s->params);
-    const bool gang = task->g->m >= static_cast<int64_t>(s->gang_edges);
+    const uint64_t inflight = s->next_ticket - s->completed;
+    const bool gang = task->g->m >= static_cast<int64_t>(s->gang_edges) ||
+                      (s->gang_queue > 0 && inflight < s->gang_queue);
     if (task->kind == IRGL_KIND_SSSP && !s->sssp_ok) return IRGL_ERR_TOO_LARGE;
     if (gang ? (task->g->n > s->gang_n || task->g->m > s->gang_m)
              : (task->g->n > s->small_n || task->g->m > s->small_m))
@@ -1353,6 +1370,7 @@ irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int3
     const uint32_t d = __atomic_load_n(&sp->done[slot], __ATOMIC_ACQUIRE);
     if (d == static_cast<uint32_t>(ticket + 1)) {
         if (st) std::memcpy(st, &sp->host_stats[slot], sizeof(irgl_stats));
+        if (s->acked[slot] != ticket + 1) ++s->completed;
         s->acked[slot] = ticket + 1;
         *done = 1;
         return IRGL_OK;

@@ -41,7 +41,7 @@ struct BatchParams {
     char *scratch;             // team t's scratch starts at scratch + t * team_bytes
     unsigned long long team_bytes;
     // offsets inside one team's scratch
-    unsigned long long off_wl0, off_wl1, off_stamp, off_far0, off_far1, off_far_flag, off_visited,
+    unsigned long long off_wl0, off_wl1, off_stamp, off_shadow, off_far0, off_far1, off_far_flag, off_visited,
         off_hub_v, off_hub_base;
     uint32_t cap;              // worklist capacity = largest n
     uint32_t hub_cap;
@@ -64,6 +64,7 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.wl1 = reinterpret_cast<int32_t *>(base + bp.off_wl1);
     const bool sssp = t.kind == 1;
     p.stamp = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_stamp) : nullptr;
+    p.shadow = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_shadow) : nullptr;
     p.far0 = sssp ? reinterpret_cast<int32_t *>(base + bp.off_far0) : nullptr;
     p.far1 = sssp ? reinterpret_cast<int32_t *>(base + bp.off_far1) : nullptr;
     p.far_flag = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_far_flag) : nullptr;

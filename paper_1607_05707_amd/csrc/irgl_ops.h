@@ -38,6 +38,7 @@ struct Params {
     uint32_t *val;        // level (BFS) or dist (SSSP)
     int32_t *parent;      // optional
     uint32_t *stamp;      // SSSP push stamps
+    uint32_t *shadow;     // SSSP probe-only copy of dist (never touched by atomics)
     int32_t *wl0;
     int32_t *wl1;
     int32_t *hub_v;       // grid tier: deferred vertices of the current invocation
@@ -137,6 +138,12 @@ struct SsspOp {
     uint32_t it;
     Ctrl *ctrl;
     const uint32_t *settled;  // bitmap of vertices whose distance is final, or null
+    // Probe-only copy of dist: an upper bound of it (every value it ever held
+    // was a tentative distance, and distances only fall), written with plain
+    // stores after a successful atomicMin and never touched by an atomic, so
+    // its lines stay cacheable in L2 while dist's lines, hammered by atomics,
+    // do not.  A relaxation that cannot beat the bound cannot improve dist.
+    uint32_t *shadow;
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],
@@ -164,11 +171,12 @@ struct SsspOp {
         }
         if (ovf) set_error(ctrl, kErrOverflow, false);
 #pragma unroll
-        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? dist[d[k]] : 0u;
+        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? shadow[d[k]] : 0u;
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             act[k] = act[k] && nd[k] < cur[k];
             if (act[k]) act[k] = nd[k] < atomicMin(&dist[d[k]], nd[k]);
+            if (act[k]) shadow[d[k]] = nd[k];
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {

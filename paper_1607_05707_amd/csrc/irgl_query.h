@@ -9,7 +9,8 @@ namespace irgl {
 
 // ---------------------------------------------------------------------------
 // Initialisation: val = INF except val[src] = 0; parent = -1 except
-// parent[src] = src; stamps = INF; far flags = 0; bitmap = {src}; in = [src];
+// parent[src] = src; stamps = INF; SSSP shadow = dist; far flags = 0;
+// bitmap = {src}; in = [src];
 // counters and stats cleared.
 // ---------------------------------------------------------------------------
 // Per-query fill, grid-strided over the team.
@@ -21,6 +22,7 @@ __device__ __forceinline__ void init_arrays(const Params &p, int with_stamp, Tea
         if (p.parent) p.parent[i] = s ? p.src_orig : -1;
         if (with_stamp) {
             p.stamp[i] = kInf;
+            p.shadow[i] = s ? 0u : kInf;
             p.far_flag[i] = 0u;
         }
         if (p.visited && (i & 31u) == 0u)
@@ -68,7 +70,7 @@ __device__ __forceinline__ Op make_op(const Params &p, uint32_t it, uint32_t thr
 
 template <>
 __device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh) {
-    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited};
+    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited, p.shadow};
 }
 
 template <>

@@ -379,7 +379,7 @@ class irgl_batch_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("team", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("t_grid", ctypes.c_int32), ("delta", ctypes.c_uint32),
                 ("watchdog_ms", ctypes.c_uint32), ("grid", ctypes.c_int32), ("barrier", ctypes.c_uint32),
-                ("gang_edges", ctypes.c_uint32)]
+                ("gang_edges", ctypes.c_uint32), ("gang_queue", ctypes.c_uint32)]
 
 
 _lib.irgl_control_block_sizes.restype = ctypes.c_int32

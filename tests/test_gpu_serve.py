@@ -74,13 +74,16 @@ def test_server_results_match_oracle_and_alone(irgl, graphs):
     server.close()
 
 
-@pytest.mark.parametrize("gang_edges,team", [(20_000, 8), (1, 4), (20_000, 10_000)])
-def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team):
-    """Tasks on graphs with at least gang_edges edges run on the whole grid
-    between the teams' own tasks; every result equals the oracle, in ring
-    order or not, and the kernel ends and relaunches between waves."""
-    print(f"[case] gang_edges={gang_edges} team={team}", flush=True)
-    server = irgl.irgl_batch_open([hg for _, hg, _ in graphs], cfg={"team": team, "gang_edges": gang_edges},
+@pytest.mark.parametrize("gang_edges,team,gang_queue", [(20_000, 8, 0), (1, 4, 0), (20_000, 10_000, 0),
+                                                        (1 << 30, 8, 6)])
+def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team, gang_queue):
+    """Tasks on graphs with at least gang_edges edges (or enqueued while fewer
+    than gang_queue are in flight) run on the whole grid between the teams'
+    own tasks; every result equals the oracle, in ring order or not, and the
+    kernel ends and relaunches between waves."""
+    print(f"[case] gang_edges={gang_edges} team={team} gang_queue={gang_queue}", flush=True)
+    server = irgl.irgl_batch_open([hg for _, hg, _ in graphs],
+                                  cfg={"team": team, "gang_edges": gang_edges, "gang_queue": gang_queue},
                                   ring_cap=32, idle_ms=5)
     rng = np.random.default_rng(gang_edges + team)
     for wave in range(2):
