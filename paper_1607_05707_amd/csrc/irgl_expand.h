@@ -27,6 +27,8 @@ struct Pushers {
     const int32_t *deg_rp;    // BFS direction choice: row offsets to sum pushed degrees, or null
     unsigned long long *mf_out;
     unsigned long long mf;    // this lane's sum of out-degrees of pushed vertices
+    uint32_t tries = 0;       // this lane's claim atomics (trace statistics)
+    uint32_t wins = 0;        // ... and the successful ones
     __device__ __forceinline__ void near(bool p, int item) {
         nq.push(p, item, sk.cnt_out, sk.out, sk.cap, sk.ctrl);
     }
@@ -79,7 +81,7 @@ __device__ __forceinline__ void relax_and_push(const Op &op, const int32_t *__re
         d[k] = act[k] ? col[e[k]] : 0;
         far[k] = false;
     }
-    op.relax(e, d, sv, sval, act, far, pu.fmin);
+    op.relax(e, d, sv, sval, act, far, pu.fmin, pu.tries, pu.wins);
     if (!Op::kFar && pu.deg_rp) {
 #pragma unroll
         for (int k = 0; k < kU; ++k)

@@ -79,7 +79,8 @@ struct Params {
 // ---------------------------------------------------------------------------
 // Relax operators.  relax(e, d, sv, sval, act) receives U scanned edges
 // e[k] = (sv[k] -> d[k]) of this lane, act[k] marking the live ones, and
-// leaves act[k] true for each destination that must be pushed.
+// leaves act[k] true for each destination that must be pushed.  `tries` /
+// `wins` count this lane's claim atomics and the successful ones.
 // ---------------------------------------------------------------------------
 struct BfsOp {
     static constexpr bool kPush = true;
@@ -93,7 +94,7 @@ struct BfsOp {
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&)[kU], const int (&d)[kU], const int (&sv)[kU],
                                           const uint32_t (&)[kU], bool (&act)[kU], bool (&)[kU],
-                                          uint32_t &) const {
+                                          uint32_t &, uint32_t &tries, uint32_t &wins) const {
         // Cheapest filter first: the n/8-byte bitmap stays resident in L2.
         // (visited is null when the bitmap is disabled: a uniform branch)
         if (visited) {
@@ -111,7 +112,9 @@ struct BfsOp {
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             act[k] = act[k] && lv[k] == kInf;
+            tries += act[k] ? 1u : 0u;
             if (act[k]) act[k] = atomicCAS(&level[d[k]], kInf, next) == kInf;
+            wins += act[k] ? 1u : 0u;
         }
         if (parent) {
 #pragma unroll
@@ -148,7 +151,7 @@ struct SsspOp {
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],
                                           const uint32_t (&dv)[kU], bool (&act)[kU],
-                                          bool (&far)[kU], uint32_t &fmin) const {
+                                          bool (&far)[kU], uint32_t &fmin, uint32_t &tries, uint32_t &wins) const {
         uint32_t nd[kU], cur[kU];
         // a settled destination cannot improve (weights >= 1): skip it with an
         // L2-resident bit test instead of a probe of dist[]
@@ -175,7 +178,9 @@ struct SsspOp {
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             act[k] = act[k] && nd[k] < cur[k];
+            tries += act[k] ? 1u : 0u;
             if (act[k]) act[k] = nd[k] < atomicMin(&dist[d[k]], nd[k]);
+            wins += act[k] ? 1u : 0u;
             if (act[k]) shadow[d[k]] = nd[k];
         }
 #pragma unroll
@@ -211,7 +216,7 @@ struct SsspParentOp {
     __device__ __forceinline__ bool active(uint32_t dv) const { return dv != kInf; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&sv)[kU],
                                           const uint32_t (&dv)[kU], bool (&act)[kU], bool (&)[kU],
-                                          uint32_t &) const {
+                                          uint32_t &, uint32_t &, uint32_t &) const {
         uint32_t s[kU], cur[kU];
 #pragma unroll
         for (int k = 0; k < kU; ++k) s[k] = act[k] ? dv[k] + w[e[k]] : 0u;

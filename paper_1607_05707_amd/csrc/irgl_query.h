@@ -127,18 +127,42 @@ __device__ __forceinline__ void add_block_total(unsigned long long x, unsigned l
     if (threadIdx.x == 0) atomicAdd(dst, s_total);
 }
 
-// Trace of invocation `it` (only when a trace buffer is given): edges this
-// workgroup scanned, and the number of vertices deferred to the grid tier.
+// Trace of invocation `it` (only when a trace buffer is given), kTraceWords
+// words at kTraceWords * it: start tick, incoming worklist size, edges
+// scanned, vertices deferred to the grid tier, start tick of the grid-tier
+// phase (0: none), claim atomics tried and won, reserved.
+constexpr uint32_t kTraceWords = 8;
+
+__device__ __forceinline__ bool tracing(const Params &p, uint32_t it) {
+    return kTraceWords * it + kTraceWords - 1 < p.trace_len;
+}
+
+__device__ __forceinline__ void trace_start(const Params &p, uint32_t it, uint32_t cnt_in) {
+    unsigned long long *t = p.trace + kTraceWords * it;
+    t[0] = wall_clock64();
+    t[1] = cnt_in;
+    for (uint32_t k = 2; k < kTraceWords; ++k) t[k] = 0;
+}
+
+// End of invocation `it`: this workgroup's edges and claim atomics.
+template <class P>
 __device__ __forceinline__ void trace_level(const Params &p, uint32_t it, unsigned long long edges,
-                                            const unsigned long long *hub_ctr, Team tm) {
-    __shared__ unsigned long long s_sum;
-    if (threadIdx.x == 0) s_sum = 0;
+                                            const unsigned long long *hub_ctr, Team tm, P &pu) {
+    __shared__ unsigned long long s_sum[3];
+    if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
     __syncthreads();
-    if (edges) atomicAdd(&s_sum, edges);
+    if (edges) atomicAdd(&s_sum[0], edges);
+    if (pu.tries) atomicAdd(&s_sum[1], static_cast<unsigned long long>(pu.tries));
+    if (pu.wins) atomicAdd(&s_sum[2], static_cast<unsigned long long>(pu.wins));
+    pu.tries = 0;
+    pu.wins = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(&p.trace[4 * it + 2], s_sum);
-        if (tm.id == 0) p.trace[4 * it + 3] = hub_ctr[0] >> 40;
+        unsigned long long *t = p.trace + kTraceWords * it;
+        atomicAdd(&t[2], s_sum[0]);
+        atomicAdd(&t[5], s_sum[1]);
+        atomicAdd(&t[6], s_sum[2]);
+        if (tm.id == 0) t[3] = hub_ctr[0] >> 40;
     }
 }
 
@@ -296,12 +320,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                 store_agent(&ctrl->far_cnt[(tr + 2) % 3], 0u);
                 store_agent(&ctrl->far_min[(tr + 2) % 3], kInf);
             }
-            if (4 * it + 3 < p.trace_len) {
-                p.trace[4 * it] = wall_clock64();
-                p.trace[4 * it + 1] = cnt_in;
-                p.trace[4 * it + 2] = 0;
-                p.trace[4 * it + 3] = 0;
-            }
+            if (tracing(p, it)) trace_start(p, it, cnt_in);
         }
         pu.sk = Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
         unsigned long long *hub_ctr = &ctrl->hub[it % 3];
@@ -351,7 +370,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                 pull = false;
             }
             bu_seen = bu_now;
-            if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
+            if (tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
         } else {
             pu.skf = far_sink(p, tr);
             pu.mf_out = &ctrl->mf[(it + 1) % 3];
@@ -370,13 +389,14 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                 hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
                            nh, nchunks);
                 if (nh > 0) {
+                    if (lead && tracing(p, it)) p.trace[kTraceWords * it + 4] = wall_clock64();
                     expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, pu, tm);
                     drain_all<B, Op>(pu, sm);
                     if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
                 }
             }
             r.fedges += r.edges - edges_before;
-            if (4 * it + 3 < p.trace_len) trace_level(p, it, r.edges - edges_before, hub_ctr, tm);
+            if (tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
         }
         const int32_t *t = in;
         in = out;
@@ -395,7 +415,7 @@ __device__ __forceinline__ void finish_query(const Params &p, const LoopResult &
     add_block_total<B>(r.fedges, &ctrl->fedges);
     if (threadIdx.x == 0) {
         if (tm.id == 0) {
-            if (4 * r.iterations < p.trace_len) p.trace[4 * r.iterations] = wall_clock64();
+            if (kTraceWords * r.iterations < p.trace_len) p.trace[kTraceWords * r.iterations] = wall_clock64();
             ctrl->iterations = r.iterations;
             ctrl->items = r.items;
             ctrl->max_frontier = r.max_frontier;
@@ -443,10 +463,7 @@ __global__ __launch_bounds__(B) void level_kernel(Params p) {
     if (cnt_in > p.cap) cnt_in = p.cap;
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl, nullptr},
                far_sink(p, p.far_tr), kInf};
-    if (blockIdx.x == 0 && tid == 0 && 4 * it + 3 < p.trace_len) {
-        p.trace[4 * it] = wall_clock64();
-        p.trace[4 * it + 1] = cnt_in;
-    }
+    if (blockIdx.x == 0 && tid == 0 && tracing(p, it)) trace_start(p, it, cnt_in);
     if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), kInf);
     const Op op = make_op<Op>(p, it, p.thresh);
     expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave, p.t_block,
@@ -494,9 +511,8 @@ __global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, u
     int32_t *out = (it & 1u) ? p.wl0 : p.wl1;
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl, nullptr},
                far_sink(p, tr + 1), kInf};
-    if (blockIdx.x == 0 && threadIdx.x == 0 && 4 * it + 3 < p.trace_len) {
-        p.trace[4 * it] = wall_clock64();
-        p.trace[4 * it + 1] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && tracing(p, it)) {
+        trace_start(p, it, 0u);
     }
     if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), p.thresh);
     far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), p.thresh, t_new, p.val,
@@ -515,7 +531,7 @@ __global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, u
 __global__ void finish_kernel(Params p, int hit_limit) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const uint32_t it = p.ctrl->iterations;
-        if (4 * it < p.trace_len) p.trace[4 * it] = wall_clock64();
+        if (kTraceWords * it < p.trace_len) p.trace[kTraceWords * it] = wall_clock64();
         if (hit_limit) set_error(p.ctrl, kErrIterLimit, false);
         publish_stats(p);
     }
