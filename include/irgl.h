@@ -149,13 +149,15 @@ typedef struct irgl_config {
                              8, 32 x mean weight / mean degree; otherwise
                              IRGL_DELTA_NONE (plain Bellman-Ford order) */
     uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
-                             Eight words per invocation i at 8i: wall-clock tick at its
-                             start, incoming worklist size, edges scanned, vertices
+                             Twelve words per invocation i at 12i: wall-clock tick at
+                             its start, incoming worklist size, edges scanned, vertices
                              deferred to the grid tier, tick at the start of the
                              grid-tier phase (0: none), claim atomics tried (BFS CAS /
-                             SSSP atomicMin), claim atomics won, 0; then the end tick
-                             at 8 x iterations.  Edges and atomics are counted in
-                             persistent mode only */
+                             SSSP atomicMin), claim atomics won, largest and summed
+                             per-workgroup busy ticks of the expansion phase, the same
+                             for the grid-tier phase, 0; then the end tick at
+                             12 x iterations.  All but the first two words are
+                             recorded by top-down invocations in persistent mode */
     uint32_t barrier;     /* grid-barrier coherence scheme: IRGL_BARRIER_XCD (default:
                              one L2 write-back per XCD per barrier) or
                              IRGL_BARRIER_WORKGROUP (write-back and invalidate per

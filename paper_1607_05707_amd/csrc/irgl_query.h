@@ -130,8 +130,10 @@ __device__ __forceinline__ void add_block_total(unsigned long long x, unsigned l
 // Trace of invocation `it` (only when a trace buffer is given), kTraceWords
 // words at kTraceWords * it: start tick, incoming worklist size, edges
 // scanned, vertices deferred to the grid tier, start tick of the grid-tier
-// phase (0: none), claim atomics tried and won, reserved.
-constexpr uint32_t kTraceWords = 8;
+// phase (0: none), claim atomics tried and won, then the largest and the
+// summed per-workgroup busy ticks of the expansion phase and of the
+// grid-tier phase (load balance), reserved.
+constexpr uint32_t kTraceWords = 12;
 
 __device__ __forceinline__ bool tracing(const Params &p, uint32_t it) {
     return kTraceWords * it + kTraceWords - 1 < p.trace_len;
@@ -147,7 +149,8 @@ __device__ __forceinline__ void trace_start(const Params &p, uint32_t it, uint32
 // End of invocation `it`: this workgroup's edges and claim atomics.
 template <class P>
 __device__ __forceinline__ void trace_level(const Params &p, uint32_t it, unsigned long long edges,
-                                            const unsigned long long *hub_ctr, Team tm, P &pu) {
+                                            const unsigned long long *hub_ctr, Team tm, P &pu,
+                                            unsigned long long busy_a = 0, unsigned long long busy_b = 0) {
     __shared__ unsigned long long s_sum[3];
     if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
     __syncthreads();
@@ -162,6 +165,10 @@ __device__ __forceinline__ void trace_level(const Params &p, uint32_t it, unsign
         atomicAdd(&t[2], s_sum[0]);
         atomicAdd(&t[5], s_sum[1]);
         atomicAdd(&t[6], s_sum[2]);
+        atomicMax(&t[7], busy_a);
+        atomicAdd(&t[8], busy_a);
+        atomicMax(&t[9], busy_b);
+        atomicAdd(&t[10], busy_b);
         if (tm.id == 0) t[3] = hub_ctr[0] >> 40;
     }
 }
@@ -380,23 +387,28 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                 refreshed = r.items;
             }
             const Op op = make_op<Op>(p, it, thresh);
+            const bool tr_on = tracing(p, it);
+            unsigned long long busy_a = tr_on ? wall_clock64() : 0ull, busy_b = 0;
             expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
                           p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm);
             drain_all<B, Op>(pu, sm);
+            if (tr_on) busy_a = wall_clock64() - busy_a;
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
             if (p.t_grid > 0) {
                 uint32_t nh, nchunks;
                 hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
                            nh, nchunks);
                 if (nh > 0) {
-                    if (lead && tracing(p, it)) p.trace[kTraceWords * it + 4] = wall_clock64();
+                    if (tr_on) busy_b = wall_clock64();
+                    if (lead && tr_on) p.trace[kTraceWords * it + 4] = busy_b;
                     expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, op, sm, pu, tm);
                     drain_all<B, Op>(pu, sm);
+                    if (tr_on) busy_b = wall_clock64() - busy_b;
                     if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
                 }
             }
             r.fedges += r.edges - edges_before;
-            if (tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
+            if (tr_on) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu, busy_a, busy_b);
         }
         const int32_t *t = in;
         in = out;

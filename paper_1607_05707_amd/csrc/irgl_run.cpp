@@ -4,7 +4,7 @@
 //
 //   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
 //                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
-//                 [--do-alpha A] [--delta D] [--calibrate MB]
+//                 [--do-alpha A] [--delta D] [--calibrate MB] [--reorder 0|1]
 //
 // --calibrate MB first copies MB megabytes device-to-device once (a plain
 // copy of known traffic, to scale hardware byte counters).
@@ -47,6 +47,7 @@ int main(int argc, char **argv) {
     std::string kinds = "bfs,sssp";
     int nsrc = 8, reps = 1, warmup = 1;
     long calib_mb = 0;
+    int reorder = 0;
     irgl_config cfg;
     std::memset(&cfg, 0, sizeof(cfg));
     for (int i = 2; i + 1 < argc; i += 2) {
@@ -62,6 +63,7 @@ int main(int argc, char **argv) {
         else if (k == "--t-bitmap") cfg.t_bitmap = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--do-alpha") cfg.do_alpha = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--delta") cfg.delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--reorder") reorder = std::atoi(v);
         else if (k == "--calibrate") calib_mb = std::atol(v);
         else {
             std::fprintf(stderr, "unknown option %s\n", k.c_str());
@@ -124,7 +126,15 @@ int main(int argc, char **argv) {
     }
     irgl_csr csr{static_cast<int32_t>(n), m, d_rp, d_col, d_w, IRGL_VALIDATE | (symmetric ? IRGL_SYMMETRIC : 0u)};
     irgl_graph g;
-    CI(irgl_graph_upload(&csr, &g));
+    void *store = nullptr;
+    if (reorder) {
+        size_t sb = 0;
+        CI(irgl_reorder_bytes(csr.n, csr.m, d_w != nullptr, &sb));
+        CK(hipMalloc(&store, sb));
+        CI(irgl_graph_upload_reordered(&csr, store, sb, &g));
+    } else {
+        CI(irgl_graph_upload(&csr, &g));
+    }
     irgl_stats *d_stats;
     CK(hipMalloc(&d_stats, sizeof(irgl_stats)));
     hipStream_t s;
@@ -186,6 +196,7 @@ int main(int argc, char **argv) {
         CK(hipFree(ws));
     }
     CI(irgl_graph_free(g));
+    if (store) CK(hipFree(store));
     CK(hipStreamDestroy(s));
     CK(hipFree(d_stats));
     CK(hipFree(d_rp));
