@@ -106,11 +106,14 @@ typedef struct irgl_graph_s *irgl_graph;
  * of the range, >= t_block -> the whole workgroup strides the neighbour
  * range, >= t_wave -> one 64-lane wavefront strides it, otherwise the
  * remaining ranges of a workgroup are concatenated by a prefix sum in LDS and
- * dealt to consecutive lanes. */
+ * dealt to the lanes in full rounds (load-balanced gather).  By default only
+ * the grid and gather tiers are used; the workgroup and wavefront tiers take
+ * ranges when their thresholds are set. */
 typedef struct irgl_config {
     int32_t block;        /* threads per workgroup: 256 (default), 512 or 1024 */
-    int32_t t_wave;       /* wavefront tier threshold, >= 1 (default 64) */
-    int32_t t_block;      /* workgroup tier threshold, >= t_wave (default = block) */
+    int32_t t_wave;       /* wavefront tier threshold, >= 1 (default: t_block, or 64
+                             when t_block is set) */
+    int32_t t_block;      /* workgroup tier threshold, >= t_wave (default: t_grid) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
                              barrier (default max(8 x block, t_block));

@@ -157,18 +157,31 @@ struct Cfg {
     uint32_t barrier;
 };
 
+// Nested-parallelism thresholds (0 = default).  Vertices with t_grid or more
+// edges go to the grid tier (IRGL_GRID_TIER_OFF: none).  By default every
+// other range goes to the load-balanced gather tier, which fills every round
+// whatever the degree mix; the workgroup (>= t_block) and wavefront
+// (>= t_wave) tiers take ranges only when the caller sets their thresholds
+// (t_wave then defaults to 64).
+void resolve_tiers(int block, int t_wave, int t_block, int t_grid, int *ow, int *ob, int *og) {
+    const int big = 2 * block * kUMax;
+    int g = t_grid ? t_grid : std::max(big, t_block);
+    if (t_grid == IRGL_GRID_TIER_OFF) g = 0;
+    const int b = t_block ? t_block : (g > 0 ? g : big);
+    const int w = t_wave ? t_wave : (t_block ? std::min(64, b) : b);
+    *ow = w;
+    *ob = b;
+    *og = g;
+}
+
 irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
     r.block = (c && c->block) ? c->block : 256;
     if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
-    r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
-    r.t_block = (c && c->t_block) ? c->t_block : r.block;
-    if (r.t_wave < 1 || r.t_block < r.t_wave) return IRGL_ERR_CONFIG;
-    // grid tier: vertices with at least this many edges are split over all
-    // workgroups (IRGL_GRID_TIER_OFF disables it)
-    r.t_grid = (c && c->t_grid) ? c->t_grid : std::max(2 * r.block * kU, r.t_block);
-    if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
-    if (r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block)) return IRGL_ERR_CONFIG;
+    resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, c ? c->t_grid : 0, &r.t_wave, &r.t_block,
+                  &r.t_grid);
+    if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
+        return IRGL_ERR_CONFIG;
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
     r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
@@ -491,10 +504,8 @@ irgl_status resolve_batch(const irgl_batch_config *c, BatchCfg *out) {
     if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
     r.team = (c && c->team) ? c->team : 16;
     if (r.team < 1) return IRGL_ERR_CONFIG;
-    r.t_wave = (c && c->t_wave) ? c->t_wave : 64;
-    r.t_block = (c && c->t_block) ? c->t_block : r.block;
-    r.t_grid = (c && c->t_grid) ? c->t_grid : std::max(2 * r.block * kU, r.t_block);
-    if (c && c->t_grid == IRGL_GRID_TIER_OFF) r.t_grid = 0;
+    resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, c ? c->t_grid : 0, &r.t_wave, &r.t_block,
+                  &r.t_grid);
     if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
         return IRGL_ERR_CONFIG;
     r.delta = c ? c->delta : 0u;

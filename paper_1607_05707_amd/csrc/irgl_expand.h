@@ -72,28 +72,28 @@ __device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
 // Relax U edges of one lane and push the survivors (all 64 lanes call it).
 template <class Op>
 __device__ __forceinline__ void relax_and_push(const Op &op, const int32_t *__restrict__ col,
-                                               const int (&e)[kU], bool (&act)[kU], const int (&sv)[kU],
-                                               const uint32_t (&sval)[kU], Pushers &pu) {
-    int d[kU];
-    bool far[kU];
+                                               const int (&e)[Op::kU], bool (&act)[Op::kU], const int (&sv)[Op::kU],
+                                               const uint32_t (&sval)[Op::kU], Pushers &pu) {
+    int d[Op::kU];
+    bool far[Op::kU];
 #pragma unroll
-    for (int k = 0; k < kU; ++k) {
+    for (int k = 0; k < Op::kU; ++k) {
         d[k] = act[k] ? col[e[k]] : 0;
         far[k] = false;
     }
     op.relax(e, d, sv, sval, act, far, pu.fmin, pu.tries, pu.wins);
     if (!Op::kFar && pu.deg_rp) {
 #pragma unroll
-        for (int k = 0; k < kU; ++k)
+        for (int k = 0; k < Op::kU; ++k)
             if (act[k]) pu.mf += static_cast<unsigned long long>(pu.deg_rp[d[k] + 1] - pu.deg_rp[d[k]]);
     }
     if (Op::kPush) {
 #pragma unroll
-        for (int k = 0; k < kU; ++k) pu.near(act[k], d[k]);
+        for (int k = 0; k < Op::kU; ++k) pu.near(act[k], d[k]);
     }
     if (Op::kFar) {
 #pragma unroll
-        for (int k = 0; k < kU; ++k) pu.far(far[k], d[k]);
+        for (int k = 0; k < Op::kU; ++k) pu.far(far[k], d[k]);
     }
 }
 
@@ -104,18 +104,18 @@ template <class Op>
 __device__ __forceinline__ void stride_range(const Op &op, const int32_t *__restrict__ col, int r0,
                                              int r1, int sv, uint32_t sval, int li, int width,
                                              Pushers &pu) {
-    int svs[kU];
-    uint32_t svals[kU];
+    int svs[Op::kU];
+    uint32_t svals[Op::kU];
 #pragma unroll
-    for (int k = 0; k < kU; ++k) {
+    for (int k = 0; k < Op::kU; ++k) {
         svs[k] = sv;
         svals[k] = sval;
     }
-    for (int e0 = r0; e0 < r1; e0 += width * kU) {
-        int e[kU];
-        bool act[kU];
+    for (int e0 = r0; e0 < r1; e0 += width * Op::kU) {
+        int e[Op::kU];
+        bool act[Op::kU];
 #pragma unroll
-        for (int k = 0; k < kU; ++k) {
+        for (int k = 0; k < Op::kU; ++k) {
             e[k] = e0 + k * width + li;
             act[k] = e[k] < r1;
         }
@@ -140,7 +140,8 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                                        uint32_t hub_cap, unsigned long long *hub_ctr,
                                        unsigned long long &edges, Team tm) {
     constexpr int NW = B / kWave;
-    constexpr int kChunk = B * kU;
+    constexpr int kChunk = B * Op::kU;
+    static_assert(Op::kU <= kUMax, "the gather window in LDS holds B * kUMax slots");
     const int tid = threadIdx.x;
     const int lane = lane_id();
     const int wid = tid / kWave;
@@ -149,7 +150,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
     // Small worklist (no more items than wavefronts in the team): one item per
     // wavefront, dealt across workgroups first, so that the ranges of a few
     // items are not walked one after another by a few workgroups.  Ranges of
-    // t_block or more edges go to the grid tier.
+    // B or more edges go to the grid tier.
     if (t_grid > 0 && cnt_in <= tm.size * NW) {
         const uint32_t i = static_cast<uint32_t>(wid) * tm.size + tm.id;
         if (i >= cnt_in) return;  // uniform across the wavefront
@@ -167,7 +168,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         }
         const int deg = r1 - r0;
         if (lane == 0) edges += static_cast<unsigned long long>(deg);
-        if (deg >= t_block) {
+        if (deg >= B) {  // a range of a whole round or more goes to the grid tier
             int listed = 0;
             if (lane == 0) {
                 const unsigned long long old = atomicAdd(
@@ -260,12 +261,13 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             stride_range(op, col, w0, w1, wv, wval, lane, kWave, pu);
         }
 
-        // Tier 3: concatenate the remaining small ranges of the workgroup with
-        // an exclusive prefix sum and deal edges to consecutive lanes.
+        // Tier 3: the remaining ranges of the workgroup are concatenated by an
+        // exclusive prefix sum and dealt to the lanes in rounds of B*U edges,
+        // every round full: slot s belongs to the last thread whose range
+        // starts at or before s (a binary search over the scan in LDS), so a
+        // workgroup needs ceil(total / (B*U)) rounds whatever the degree mix.
         const int incl = wave_inclusive_scan(deg);
         if (lane == kWave - 1) sm.wsum[wid] = incl;
-        sm.vtx[tid] = v;
-        sm.vval[tid] = val;
         __syncthreads();
         int total = 0, wpre = 0;
 #pragma unroll
@@ -274,30 +276,30 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             wpre += (k < wid) ? s : 0;
             total += s;
         }
-        const int excl = wpre + incl - deg;
+        sm.gstart[tid] = wpre + incl - deg;
+        sm.gr0[tid] = r0;
+        sm.vtx[tid] = v;
+        sm.vval[tid] = val;
+        __syncthreads();
         for (int done = 0; done < total; done += kChunk) {
-            const int lo = max(excl, done);
-            const int hi = min(excl + deg, done + kChunk);
-            for (int k = lo; k < hi; ++k) {
-                sm.gather_edge[k - done] = r0 + (k - excl);
-                sm.gather_owner[k - done] = static_cast<uint16_t>(tid);
-            }
-            __syncthreads();
-            int e[kU], sv[kU];
-            uint32_t sval[kU];
-            bool act[kU];
+            int e[Op::kU], sv[Op::kU];
+            uint32_t sval[Op::kU];
+            bool act[Op::kU];
 #pragma unroll
-            for (int k = 0; k < kU; ++k) {
-                const int slot = k * B + tid;
-                act[k] = slot < total - done;
-                const int o = act[k] ? sm.gather_owner[slot] : 0;
-                e[k] = act[k] ? sm.gather_edge[slot] : 0;
+            for (int k = 0; k < Op::kU; ++k) {
+                const int slot = done + k * B + tid;
+                act[k] = slot < total;
+                int o = 0;
+#pragma unroll
+                for (int step = B / 2; step > 0; step >>= 1)
+                    if (sm.gstart[o + step] <= slot) o += step;
+                e[k] = act[k] ? sm.gr0[o] + (slot - sm.gstart[o]) : 0;
                 sv[k] = sm.vtx[o];
                 sval[k] = sm.vval[o];
             }
             relax_and_push(op, col, e, act, sv, sval, pu);
-            __syncthreads();
         }
+        __syncthreads();  // the scan arrays are rewritten by the next tile
     }
 }
 
@@ -311,7 +313,7 @@ __device__ __forceinline__ void expand_hubs(uint32_t nhubs, uint32_t nchunks, co
                                             const int32_t *__restrict__ row_ptr,
                                             const int32_t *__restrict__ col, const Op &op, Smem<B> &sm,
                                             Pushers &pu, Team tm) {
-    constexpr int kChunk = B * kU;
+    constexpr int kChunk = B * Op::kU;
     const unsigned long long G = tm.size;
     const uint32_t lo = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(tm.id) / G);
     const uint32_t hi = static_cast<uint32_t>(nchunks * static_cast<unsigned long long>(tm.id + 1) / G);

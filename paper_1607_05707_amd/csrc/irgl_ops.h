@@ -8,14 +8,14 @@ namespace irgl {
 
 
 constexpr int kQueueCap = 256;  // LDS staging entries per wavefront
-constexpr int kU = 4;           // edges per lane per round (memory-level parallelism)
+constexpr int kUMax = 4;        // largest edges-per-lane-per-round of any operator
 
 // Shared-memory layout of the frontier kernels for workgroup size B.
 template <int B>
 struct Smem {
     static constexpr int NW = B / kWave;
-    int gather_edge[B * kU];       // edge index of each slot of the current gather window
-    uint16_t gather_owner[B * kU]; // thread whose vertex owns that edge
+    int gstart[B];                 // gather tier: first slot of each thread's range (exclusive scan)
+    int gr0[B];                    // gather tier: first edge of each thread's range
     int vtx[B];                    // popped vertex of each thread
     uint32_t vval[B];              // its per-vertex value (SSSP distance at pop)
     int wsum[NW];                  // per-wavefront degree sums for the workgroup scan
@@ -85,6 +85,10 @@ struct Params {
 struct BfsOp {
     static constexpr bool kPush = true;
     static constexpr bool kFar = false;
+    // edges per lane per round (memory-level parallelism) and the fewest
+    // waves per SIMD the persistent kernel must fit (1: no register cap)
+    static constexpr int kU = 4;
+    static constexpr int kMinWaves = 1;
     uint32_t *level;
     int32_t *parent;
     const uint32_t *visited;  // bitmap: a set bit means "visited" (never a false positive)
@@ -133,6 +137,12 @@ struct BfsOp {
 struct SsspOp {
     static constexpr bool kPush = true;
     static constexpr bool kFar = true;
+    // Measured on RMAT-22: 2 edges per lane and a register cap that fits 5
+    // waves per SIMD (1280 workgroups instead of 768) beat 4 edges per lane:
+    // each relaxation is a chain of dependent loads, so more waves in flight
+    // hide more latency than more edges per wave.
+    static constexpr int kU = 2;
+    static constexpr int kMinWaves = 5;
     uint32_t *dist;
     const uint32_t *w;
     uint32_t *stamp;
@@ -207,6 +217,8 @@ struct SsspOp {
 struct SsspParentOp {
     static constexpr bool kPush = false;
     static constexpr bool kFar = false;
+    static constexpr int kU = 4;
+    static constexpr int kMinWaves = 1;
     const uint32_t *dist;
     const uint32_t *w;
     int32_t *parent;

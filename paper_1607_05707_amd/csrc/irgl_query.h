@@ -241,17 +241,17 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
             r1 = p.row_ptr[v + 1];
         }
         int found = -1;
-        for (int e0 = r0; e0 < r1; e0 += kU) {
-            int u[kU];
-            uint32_t fw[kU];
+        for (int e0 = r0; e0 < r1; e0 += kUMax) {
+            int u[kUMax];
+            uint32_t fw[kUMax];
 #pragma unroll
-            for (int k = 0; k < kU; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
+            for (int k = 0; k < kUMax; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
 #pragma unroll
-            for (int k = 0; k < kU; ++k) fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
+            for (int k = 0; k < kUMax; ++k) fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
 #pragma unroll
-            for (int k = 0; k < kU; ++k)
+            for (int k = 0; k < kUMax; ++k)
                 if (found < 0 && u[k] >= 0 && ((fw[k] >> (u[k] & 31)) & 1u)) found = u[k];
-            scanned += static_cast<unsigned long long>(min(kU, r1 - e0));
+            scanned += static_cast<unsigned long long>(min(kUMax, r1 - e0));
             if (found >= 0) break;
         }
         if (found >= 0) {
@@ -445,7 +445,8 @@ __device__ __forceinline__ void finish_query(const Params &p, const LoopResult &
 
 // One query per cooperative launch: the whole grid is the team.
 template <int B, class Op>
-__global__ __launch_bounds__(B) void persistent_kernel(Params p) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(Op::kMinWaves))) void persistent_kernel(
+    Params p) {
     __shared__ Smem<B> sm;
     const Team tm = whole_grid();
     BarrierState bs = make_barrier_state(p.wd_ticks, p.barrier);
