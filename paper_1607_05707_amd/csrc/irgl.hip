@@ -533,7 +533,9 @@ irgl_status check_tasks(const irgl_task *tasks, int32_t ntasks) {
 }
 
 template <int B>
-irgl_status batch_grid(int dev, int requested, int *grid) {
+irgl_status batch_grid(int dev, int requested, int *grid, bool server) {
+    // the two control kernels differ in register use, hence in co-residency
+    if (server) return coresident_grid(server_kernel<B>, B, dev, requested, grid);
     return coresident_grid(batch_kernel<B>, B, dev, requested, grid);
 }
 
@@ -562,15 +564,15 @@ void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, BatchL
 // Team layout for graphs of at most nmax vertices / mmax edges; `records`
 // per-task statistics slots (batch: tasks, server: ring slots).
 irgl_status team_layout(int64_t nmax, int64_t mmax, bool any_sssp, bool any_bfs, int32_t records,
-                        const BatchCfg &c, int dev, BatchLayout *out) {
+                        const BatchCfg &c, int dev, BatchLayout *out, bool server = false) {
     BatchLayout L;
     nmax = std::max<int64_t>(nmax, 1);
     int grid = 0;
     irgl_status st = IRGL_OK;
     switch (c.block) {
-        case 256: st = batch_grid<256>(dev, c.grid, &grid); break;
-        case 512: st = batch_grid<512>(dev, c.grid, &grid); break;
-        default: st = batch_grid<1024>(dev, c.grid, &grid); break;
+        case 256: st = batch_grid<256>(dev, c.grid, &grid, server); break;
+        case 512: st = batch_grid<512>(dev, c.grid, &grid, server); break;
+        default: st = batch_grid<1024>(dev, c.grid, &grid, server); break;
     }
     if (st) return st;
     const int team = std::min(c.team, grid);
@@ -1171,7 +1173,8 @@ static irgl_status server_plan(const irgl_graph *graphs, int32_t ngraphs, const 
         }
         P.weighted |= graphs[i]->w != nullptr;
     }
-    irgl_status st = team_layout(P.small_n, P.small_m, P.weighted, true, ring_cap, c, graphs[0]->device, &P.L);
+    irgl_status st =
+        team_layout(P.small_n, P.small_m, P.weighted, true, ring_cap, c, graphs[0]->device, &P.L, true);
     if (st) return st;
     P.G = P.L;
     if (P.gang_n > 0) region_layout(P.gang_n, P.gang_m, P.weighted, c.t_grid, &P.G);
