@@ -116,8 +116,9 @@ typedef struct irgl_config {
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default: t_grid) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
-                             barrier (default max(8 x block, t_block));
-                             IRGL_GRID_TIER_OFF = never */
+                             barrier (default max(2 x block, t_block); lowered to
+                             block for a worklist with fewer items than the grid has
+                             threads); IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
     int32_t mode;         /* IRGL_MODE_* */
     uint32_t max_iter;    /* safety cap on invocations (default n + 1 for BFS,

@@ -1,7 +1,7 @@
 """Autotuner for the batched launch.
 
 Picks the workgroup size (from T_control, the sizes both loop bodies
-support), the team size and the nested-parallelism thresholds by timing
+support), the team size and the grid-tier threshold by timing
 whole batches of a workload built from a HELD-OUT seed, one coordinate at a
 time, and caches the winner per device and workload class in a JSON file.
 
@@ -23,7 +23,7 @@ from . import irgl
 # tuned configurations, committed with the package (written by this module's main)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
-DEFAULT = {"block": 256, "team": 16, "t_wave": 64, "t_grid": 0}
+DEFAULT = {"block": 256, "team": 16, "t_grid": 0}
 
 
 def batch_tasks(seed: int, count: int, device, rmat_scale: int = 20, rmat_sources: int = 64,
@@ -70,8 +70,7 @@ def tune(tasks, log=print):
     space = {
         "block": irgl.irgl_control_block_sizes(),
         "team": [4, 8, 16, 32, 64],
-        "t_wave": [32, 64, 128],
-        "t_grid": [0, 4096, 16384, -1],
+        "t_grid": [0, 512, 1024, 4096, 16384, -1],
     }
     cur = dict(DEFAULT)
     cur_t = time_batch(tasks, cur)

@@ -164,7 +164,7 @@ struct Cfg {
 // (>= t_wave) tiers take ranges only when the caller sets their thresholds
 // (t_wave then defaults to 64).
 void resolve_tiers(int block, int t_wave, int t_block, int t_grid, int *ow, int *ob, int *og) {
-    const int big = 2 * block * kUMax;
+    const int big = 2 * block;
     int g = t_grid ? t_grid : std::max(big, t_block);
     if (t_grid == IRGL_GRID_TIER_OFF) g = 0;
     const int b = t_block ? t_block : (g > 0 ? g : big);
@@ -210,6 +210,14 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
     return IRGL_OK;
 }
 
+// Grid-tier list capacity: a vertex is deferred with t_grid or more edges,
+// or with `block` or more when the worklist is small, so at most
+// m / min(t_grid, block) + 1 vertices are listed.
+uint32_t grid_list_cap(int64_t n, int64_t m, int t_grid, int block) {
+    if (t_grid <= 0) return 0u;
+    return static_cast<uint32_t>(std::min<int64_t>(n, m / std::min(t_grid, block) + 1));
+}
+
 struct Layout {
     size_t ctrl, wl0, wl1, stamp, shadow, far0, far1, far_flag, visited, frontier, hub_v, hub_base, rval, rparent,
         total;
@@ -234,10 +242,7 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     const bool bitmap = c.t_bitmap != IRGL_BITMAP_NEVER || pull;
     L.frontier = L.visited + (bitmap ? bm : 0);
     L.hub_v = L.frontier + (pull ? bm : 0);
-    // at most m / t_grid vertices have t_grid or more edges
-    L.hub_cap = c.t_grid > 0
-                    ? static_cast<uint32_t>(std::min<int64_t>(g->n, g->m / c.t_grid + 1))
-                    : 0u;
+    L.hub_cap = grid_list_cap(g->n, g->m, c.t_grid, c.block);
     L.hub_base = L.hub_v + align_up(static_cast<size_t>(L.hub_cap) * 4);
     // relabelled graph: values and parents under internal ids, scattered at the end
     L.rval = L.hub_base + align_up(static_cast<size_t>(L.hub_cap) * 4);
@@ -542,10 +547,10 @@ irgl_status batch_grid(int dev, int requested, int *grid, bool server) {
 // One team's (or the gang's) scratch region for graphs of at most nmax
 // vertices / mmax edges: control block, claimed descriptor (and gang
 // record), worklists, SSSP arrays, bitmap and grid-tier list.
-void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, BatchLayout *L) {
+void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, int block, BatchLayout *L) {
     nmax = std::max<int64_t>(nmax, 1);
     L->cap = static_cast<uint32_t>(nmax);
-    L->hub_cap = t_grid > 0 ? static_cast<uint32_t>(std::min<int64_t>(nmax, mmax / t_grid + 1)) : 0u;
+    L->hub_cap = grid_list_cap(nmax, mmax, t_grid, block);
     const size_t nb = align_up(static_cast<size_t>(nmax) * 4);
     size_t o = align_up(sizeof(Ctrl) + sizeof(GangInfo));
     L->off_wl0 = o;  o += nb;
@@ -578,7 +583,7 @@ irgl_status team_layout(int64_t nmax, int64_t mmax, bool any_sssp, bool any_bfs,
     const int team = std::min(c.team, grid);
     L.team = team;
     L.teams = grid / team;
-    region_layout(nmax, mmax, any_sssp, c.t_grid, &L);
+    region_layout(nmax, mmax, any_sssp, c.t_grid, c.block, &L);
     L.queue = 0;
     L.team_task = align_up(4);
     L.tasks = L.team_task + align_up(static_cast<size_t>(L.teams) * 4);
@@ -1177,8 +1182,8 @@ static irgl_status server_plan(const irgl_graph *graphs, int32_t ngraphs, const 
         team_layout(P.small_n, P.small_m, P.weighted, true, ring_cap, c, graphs[0]->device, &P.L, true);
     if (st) return st;
     P.G = P.L;
-    if (P.gang_n > 0) region_layout(P.gang_n, P.gang_m, P.weighted, c.t_grid, &P.G);
-    else region_layout(1, 0, false, 0, &P.G);  // the gang control block is always there (exit gangs)
+    if (P.gang_n > 0) region_layout(P.gang_n, P.gang_m, P.weighted, c.t_grid, c.block, &P.G);
+    else region_layout(1, 0, false, 0, c.block, &P.G);  // the gang control block is always there (exit gangs)
     P.gang_off = P.L.total;
     P.total = P.gang_off + P.G.team_bytes;
     *out = P;

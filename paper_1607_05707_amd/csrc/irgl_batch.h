@@ -145,7 +145,7 @@ __device__ __forceinline__ bool run_task(const BatchParams &bp, const TaskDesc &
         const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
         expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr,
                                 p.col, op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, pe,
-                                tm);
+                                tm, nullptr);
         if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) return false;
     }
     if (leader) write_task_stats(p, r, tm, B);

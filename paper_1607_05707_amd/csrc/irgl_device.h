@@ -39,7 +39,9 @@ struct alignas(128) Ctrl {
     unsigned long long mf[3];
     // BFS: edges scanned by bottom-up invocations so far (grows, never reset)
     unsigned long long bu_scan;
-    uint32_t pad0[8];
+    // rotating worklist-tile counters (tiles taken beyond each workgroup's first)
+    uint32_t tile[3];
+    uint32_t pad0[5];
     // line 1: barrier generation (the only word waiting workgroups poll)
     uint32_t bar_gen;
     uint32_t pad1[31];

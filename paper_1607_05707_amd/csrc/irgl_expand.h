@@ -138,7 +138,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                                        Pushers &pu, int t_wave,
                                        int t_block, int t_grid, int32_t *hub_v, uint32_t *hub_base,
                                        uint32_t hub_cap, unsigned long long *hub_ctr,
-                                       unsigned long long &edges, Team tm) {
+                                       unsigned long long &edges, Team tm, uint32_t *tile_ctr) {
     constexpr int NW = B / kWave;
     constexpr int kChunk = B * Op::kU;
     static_assert(Op::kU <= kUMax, "the gather window in LDS holds B * kUMax slots");
@@ -186,7 +186,16 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         return;
     }
 
-    for (uint32_t base = tm.id * B; base < cnt_in; base += stride) {
+    // A worklist with fewer items than the team has threads leaves whole
+    // workgroups without a tile while others walk long ranges: then every
+    // range of a round (B edges) or more goes to the balanced grid tier.
+    if (t_grid > B && cnt_in < stride) t_grid = B;
+    // Tiles of B items: first one per workgroup, then (with tile_ctr) taken
+    // from a shared counter, so that workgroups with light tiles take more.
+    uint32_t tile = tm.id;
+    for (;;) {
+        const uint32_t base = tile * B;
+        if (base >= cnt_in) break;  // uniform across the workgroup
         const uint32_t i = base + tid;
         int v = -1, r0 = 0, r1 = 0;
         uint32_t val = 0;
@@ -299,7 +308,11 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             }
             relax_and_push(op, col, e, act, sv, sval, pu);
         }
-        __syncthreads();  // the scan arrays are rewritten by the next tile
+        if (tile_ctr) {
+            if (tid == 0) sm.tile = tm.size + atomicAdd(tile_ctr, 1u);
+        }
+        __syncthreads();  // the scan arrays are rewritten by the next tile; sm.tile is set
+        tile = tile_ctr ? sm.tile : tile + tm.size;
     }
 }
 

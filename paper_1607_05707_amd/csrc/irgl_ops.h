@@ -28,6 +28,7 @@ struct Smem {
     uint32_t base;
     int flag;
     int hub_h;                     // grid tier: first deferred vertex of this workgroup
+    uint32_t tile;                 // next worklist tile of this workgroup
 };
 
 struct Params {

@@ -40,6 +40,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
         c->cnt[1] = 0;
         c->cnt[2] = 0;
         for (int k = 0; k < 3; ++k) {
+            c->tile[k] = 0;
             c->hub[k] = 0;
             c->far_cnt[k] = 0;
             c->far_min[k] = kInf;
@@ -321,6 +322,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
         r.max_frontier = max(r.max_frontier, cnt_in);
         if (lead) {
             store_agent(&ctrl->cnt[(it + 2) % 3], 0u);
+            store_agent(&ctrl->tile[(it + 2) % 3], 0u);
             __hip_atomic_store(&ctrl->hub[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctrl->mf[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (cnt_in == 0) {
@@ -390,7 +392,8 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             const bool tr_on = tracing(p, it);
             unsigned long long busy_a = tr_on ? wall_clock64() : 0ull, busy_b = 0;
             expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
-                          p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm);
+                          p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm,
+                          &ctrl->tile[it % 3]);
             drain_all<B, Op>(pu, sm);
             if (tr_on) busy_a = wall_clock64() - busy_a;
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
@@ -480,12 +483,14 @@ __global__ __launch_bounds__(B) void level_kernel(Params p) {
     if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), kInf);
     const Op op = make_op<Op>(p, it, p.thresh);
     expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave, p.t_block,
-                  p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges, whole_grid());
+                  p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges, whole_grid(),
+                  &ctrl->tile[it % 3]);
     drain_all<B, Op>(pu, sm);
     add_block_total<B>(edges, &ctrl->edges);
     add_block_total<B>(edges, &ctrl->fedges);  // top-down only: every worklist edge is scanned
     if (tid == 0 && blockIdx.x == 0) {
         ctrl->cnt[(it + 2) % 3] = 0;
+        ctrl->tile[(it + 2) % 3] = 0;
         ctrl->hub[(it + 2) % 3] = 0;
         ctrl->iterations = it + 1;
         ctrl->items += cnt_in;
@@ -533,6 +538,7 @@ __global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, u
     drain_all<B, SsspOp>(pu, sm);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->cnt[(it + 2) % 3] = 0;
+        ctrl->tile[(it + 2) % 3] = 0;
         ctrl->hub[(it + 2) % 3] = 0;
         ctrl->far_cnt[(tr + 2) % 3] = 0;
         ctrl->far_min[(tr + 2) % 3] = kInf;
@@ -562,7 +568,7 @@ __global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
     const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
     expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr, p.col,
                             op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, edges,
-                            whole_grid());
+                            whole_grid(), nullptr);
 }
 
 // Relabelled graph: results computed under internal ids (vals, parents

@@ -144,11 +144,11 @@ def test_star_hub_and_long_path(irgl):
     _check_query(irgl, gp, hp, SSSP, k // 3)
 
 
-def test_small_frontier_wave_per_item_and_hub_overflow(irgl):
+def test_small_frontier_wave_per_item_and_grid_tier(irgl):
     """A worklist with no more items than wavefronts is dealt one item per
-    wavefront; its ranges of t_block or more edges go to the grid tier, and
-    those beyond the grid-tier list's capacity (m / t_grid + 1) are expanded
-    by their wavefront."""
+    wavefront, and one with fewer items than threads sends every range of a
+    round or more to the grid tier; both give the oracle's result with
+    ranges of every size, several block sizes and thresholds."""
     rng = np.random.default_rng(11)
     degs = [100, 300, 700, 1500, 2500, 5000]
     src, dst = [], []
@@ -169,7 +169,8 @@ def test_small_frontier_wave_per_item_and_hub_overflow(irgl):
     w = rng.integers(1, 50, len(src)).tolist()
     g = _dev(gg.from_edges(n, src, dst, w, name="two_level"))
     hg = irgl.upload(g)
-    for cfg in (None, {"block": 512}, {"block": 256, "mode": 1}, {"t_grid": 4096}):
+    for cfg in (None, {"block": 512}, {"block": 256, "mode": 1}, {"t_grid": 4096}, {"t_grid": -1},
+                {"t_wave": 32, "t_block": 128, "t_grid": 1024}, {"grid": 7}):
         _check_query(irgl, g, hg, BFS, 0, cfg)
         _check_query(irgl, g, hg, SSSP, 0, cfg)
 
