@@ -466,7 +466,6 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.t_block = c.t_block;
     p.src = g->perm ? g->inv_host[static_cast<size_t>(src)] : src;
     p.src_orig = src;
-    p.balance = 1u;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (kind == IRGL_KIND_BFS) st = dispatch_block<BfsOp>(g, p, c, s, kind);
     else st = dispatch_block<SsspOp>(g, p, c, s, kind);
@@ -698,7 +697,6 @@ void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const 
     bp.t_grid = c.t_grid;
     bp.wd_ticks = static_cast<unsigned long long>(c.watchdog_ms) * di.wallclock_khz;
     bp.barrier = c.barrier;
-    bp.balance = 1u;
 }
 
 template <int B>
@@ -1268,10 +1266,6 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sp->gang.cap = P.G.cap;
     sp->gang.hub_cap = P.G.hub_cap;
     sp->gang.team = L.teams * L.team;
-    // server tasks keep static tiles and the configured grid tier (the
-    // balancing of expand() is not enabled for open batches)
-    sp->bp.balance = 0u;
-    sp->gang.balance = 0u;
     sp->ring = reinterpret_cast<TaskDesc *>(h);
     sp->tail = reinterpret_cast<uint32_t *>(h + ring_b);
     sp->stop = reinterpret_cast<uint32_t *>(h + ring_b + 128);

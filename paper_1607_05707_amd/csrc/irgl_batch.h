@@ -49,7 +49,6 @@ struct BatchParams {
     int32_t t_wave, t_block, t_grid;
     unsigned long long wd_ticks;
     uint32_t barrier;  // grid-barrier coherence scheme (kBar*)
-    uint32_t balance;  // shared tile counter / small-worklist grid tier (Params::balance)
 };
 
 __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskDesc &t, char *base) {
@@ -95,7 +94,6 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.thresh = p.delta;
     p.far_tr = 0;
     p.refresh = 0;
-    p.balance = bp.balance;
     p.frontier = nullptr;  // batched BFS runs top-down
     p.do_alpha = 0;
     p.do_beta = 0;
@@ -147,7 +145,7 @@ __device__ __forceinline__ bool run_task(const BatchParams &bp, const TaskDesc &
         const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
         expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr,
                                 p.col, op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, pe,
-                                tm, nullptr, false);
+                                tm, nullptr);
         if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) return false;
     }
     if (leader) write_task_stats(p, r, tm, B);

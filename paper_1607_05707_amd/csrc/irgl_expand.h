@@ -138,8 +138,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                                        Pushers &pu, int t_wave,
                                        int t_block, int t_grid, int32_t *hub_v, uint32_t *hub_base,
                                        uint32_t hub_cap, unsigned long long *hub_ctr,
-                                       unsigned long long &edges, Team tm, uint32_t *tile_ctr,
-                                       bool balance) {
+                                       unsigned long long &edges, Team tm, uint32_t *tile_ctr) {
     constexpr int NW = B / kWave;
     constexpr int kChunk = B * Op::kU;
     static_assert(Op::kU <= kUMax, "the gather window in LDS holds B * kUMax slots");
@@ -190,8 +189,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
     // A worklist with fewer items than the team has threads leaves whole
     // workgroups without a tile while others walk long ranges: then every
     // range of a round (B edges) or more goes to the balanced grid tier.
-    if (balance && t_grid > B && cnt_in < stride) t_grid = B;
-    if (!balance) tile_ctr = nullptr;
+    if (t_grid > B && cnt_in < stride) t_grid = B;
     // Tiles of B items: first one per workgroup, then (with tile_ctr) taken
     // from a shared counter, so that workgroups with light tiles take more.
     uint32_t tile = tm.id;

@@ -71,7 +71,6 @@ struct Params {
     uint32_t thresh;      // host-loop mode: current threshold
     uint32_t far_tr;      // host-loop mode: threshold raises so far
     uint32_t refresh;     // host-loop mode: refresh the bitmap in this invocation
-    uint32_t balance;     // shared tile counter and grid tier for small worklists (see expand)
     uint32_t *frontier;   // BFS bottom-up: bitmap of the current frontier, or null (top-down only)
     uint32_t do_alpha;    // BFS direction choice (see irgl_config)
     uint32_t do_beta;

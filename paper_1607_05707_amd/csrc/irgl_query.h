@@ -393,7 +393,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             unsigned long long busy_a = tr_on ? wall_clock64() : 0ull, busy_b = 0;
             expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
                           p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm,
-                          &ctrl->tile[it % 3], p.balance != 0);
+                          &ctrl->tile[it % 3]);
             drain_all<B, Op>(pu, sm);
             if (tr_on) busy_a = wall_clock64() - busy_a;
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(B) void level_kernel(Params p) {
     const Op op = make_op<Op>(p, it, p.thresh);
     expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave, p.t_block,
                   p.t_grid, p.hub_v, p.hub_base, p.hub_cap, &ctrl->hub[it % 3], edges, whole_grid(),
-                  &ctrl->tile[it % 3], p.balance != 0);
+                  &ctrl->tile[it % 3]);
     drain_all<B, Op>(pu, sm);
     add_block_total<B>(edges, &ctrl->edges);
     add_block_total<B>(edges, &ctrl->fedges);  // top-down only: every worklist edge is scanned
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(B) void sssp_parent_kernel(Params p) {
     const SsspParentOp op{p.val, p.w, p.parent, p.src, p.perm};
     expand<B, SsspParentOp>(nullptr, static_cast<uint32_t>(p.n), static_cast<uint32_t>(p.n), p.row_ptr, p.col,
                             op, sm, pu, p.t_wave, p.t_block, 0, nullptr, nullptr, 0u, nullptr, edges,
-                            whole_grid(), nullptr, false);
+                            whole_grid(), nullptr);
 }
 
 // Relabelled graph: results computed under internal ids (vals, parents
