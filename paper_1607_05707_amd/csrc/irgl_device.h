@@ -208,11 +208,12 @@ __device__ __forceinline__ void block_drain(WaveQueue<QCAP> &wq, int *s_fill, ui
 //   kBarWorkgroup: every arrival is an agent-scope acq_rel RMW (an L2
 //     write-back and invalidate per workgroup), then an acquire on exit.
 //   kBarXcd: the hardware deals workgroups round-robin to the XCDs, so group
-//     b mod 8 is exactly one XCD's workgroups and they share one L2.  A
-//     workgroup's stores have reached that L2 when it arrives (its
-//     __syncthreads waits for them), so ONE write-back by the group's last
-//     arrival covers the whole group; every workgroup still takes an acquire
-//     (L1 + L2 invalidate) on exit.  (Measured at 1024 workgroups: 9.3 us
+//     b mod 8 is exactly one XCD's workgroups and they share one L2.  Every
+//     wave first waits until its own stores are acknowledged by that L2
+//     (s_waitcnt: __syncthreads alone does not wait for stores), so when a
+//     workgroup arrives its stores are in the L2 and ONE write-back by the
+//     group's last arrival covers the whole group; every workgroup still
+//     takes an acquire (L1 + L2 invalidate) on exit.  (Measured at 1024 workgroups: 9.3 us
 //     per barrier against 22.8 us for kBarWorkgroup, no stale reads.  Doing
 //     the invalidate once per XCD and dropping only each CU's L1 measured
 //     faster but read stale data, so every workgroup keeps its acquire.)
@@ -269,6 +270,7 @@ __device__ __forceinline__ Team whole_grid() { return Team{blockIdx.x, gridDim.x
 
 __device__ __forceinline__ bool grid_barrier(Ctrl *ctrl, BarrierState &bs, int *s_flag,
                                              const volatile int32_t *abort_flag, Team tm) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the L2
     __syncthreads();
     if (threadIdx.x == 0) {
         if (bs.epoch == 0 && xcc_id() != blockIdx.x % kBarGroups) atomicOr(&ctrl->xmap_bad, 1u);
