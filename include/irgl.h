@@ -365,6 +365,14 @@ irgl_status irgl_batch_enqueue(irgl_server s, const irgl_task *task, uint64_t *t
  * Relaunches the server kernel if it has ended with work pending. */
 irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int32_t *done);
 
+/* Server kernel launches so far (*launches), and how many of them gave up
+ * at their start check (*gave_up): the grid barrier needs every workgroup
+ * resident, so a launch whose workgroups are not all running within a few
+ * milliseconds (a kernel on another stream holds part of the device) ends
+ * before it claims any descriptor, and the next irgl_batch_enqueue or
+ * irgl_batch_poll launches it again.  Diagnostics only. */
+irgl_status irgl_batch_launches(irgl_server s, uint64_t *launches, uint64_t *gave_up);
+
 /* Stop the server kernel, wait for it and release the handle. */
 irgl_status irgl_batch_close(irgl_server s);
 

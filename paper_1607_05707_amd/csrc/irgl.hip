@@ -55,6 +55,7 @@ struct irgl_server_s {
     void *host_mem;          // pinned: ring | tail | stop | done[] | stats[]
     void *params;            // ServerParams (host copy reused for launches)
     uint64_t *acked;         // per ring slot: 1 + the last ticket polled as done
+    uint64_t launches;       // server kernel launches so far
 };
 
 struct irgl_graph_s {
@@ -496,6 +497,11 @@ struct BatchLayout {
 // 16-workgroup team busy ~50x longer than the whole grid does.
 constexpr uint32_t kDefaultGangEdges = 1u << 23;
 
+// Server start check: a launch whose workgroups are not all resident within
+// this many milliseconds (another kernel holds part of the device) gives up
+// before claiming anything and is launched again while work is pending.
+constexpr uint32_t kServerStartMs = 10;
+
 struct BatchCfg {
     int block, team, t_wave, t_block, t_grid, grid;
     uint32_t delta, watchdog_ms, barrier;
@@ -611,8 +617,8 @@ irgl_status batch_layout(const irgl_task *tasks, int32_t ntasks, const BatchCfg 
 __global__ void zero_head_kernel(unsigned long long *w) { *w = 0ull; }
 
 // Before every server launch: team barrier words, the gang control block's
-// barrier words, and the head word's gang count / pending bit (the claimed
-// count is kept).
+// barrier words and start check, and the head word's gang count / pending
+// bit (the claimed count is kept).
 __global__ void server_reset_kernel(char *scratch, unsigned long long team_bytes, int teams, Ctrl *gang,
                                     unsigned long long *head) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -625,6 +631,9 @@ __global__ void server_reset_kernel(char *scratch, unsigned long long team_bytes
         reset_barrier_words(gang);
         gang->fatal = 0;
         gang->error = 0;
+        GangInfo *gi = reinterpret_cast<GangInfo *>(reinterpret_cast<char *>(gang) + sizeof(Ctrl));
+        gi->start_count = 0;
+        gi->start_state = 0;
         *head &= 0xFFFFFFFFull;
     }
 }
@@ -1269,11 +1278,13 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sp->ring = reinterpret_cast<TaskDesc *>(h);
     sp->tail = reinterpret_cast<uint32_t *>(h + ring_b);
     sp->stop = reinterpret_cast<uint32_t *>(h + ring_b + 128);
+    sp->start_fails = reinterpret_cast<uint32_t *>(h + ring_b + 64);
     sp->done = reinterpret_cast<uint32_t *>(h + ring_b + 256);
     sp->host_stats = reinterpret_cast<Stats *>(h + ring_b + 256 + done_b);
     sp->head = reinterpret_cast<unsigned long long *>(base + L.queue);
     sp->ring_cap = static_cast<uint32_t>(ring_cap);
     sp->idle_ticks = static_cast<unsigned long long>(idle_ms) * di.wallclock_khz;
+    sp->start_ticks = static_cast<unsigned long long>(kServerStartMs) * di.wallclock_khz;
     sv->device = dev;
     sv->stream = static_cast<hipStream_t>(stream);
     sv->launched = false;
@@ -1292,6 +1303,7 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sv->gang_edges = c.gang_edges;
     sv->gang_queue = c.gang_queue;
     sv->completed = 0;
+    sv->launches = 0;
     sv->host_mem = hm;
     sv->params = sp;
     if (hipEventCreateWithFlags(&sv->ran, hipEventDisableTiming) != hipSuccess) {
@@ -1330,6 +1342,7 @@ static irgl_status server_launch(irgl_server_s *sv) {
     if (st) return st;
     IRGL_HIP(hipEventRecord(sv->ran, sv->stream));
     sv->launched = true;
+    ++sv->launches;
     return IRGL_OK;
 }
 
@@ -1402,6 +1415,14 @@ irgl_status irgl_batch_poll(irgl_server s, uint64_t ticket, irgl_stats *st, int3
     const irgl_status k = server_kick(s, true);
     if (cur != s->device) (void)hipSetDevice(cur);
     return k;
+}
+
+irgl_status irgl_batch_launches(irgl_server s, uint64_t *launches, uint64_t *gave_up) {
+    if (!s || !launches || !gave_up) return IRGL_ERR_INVALID_ARGUMENT;
+    const ServerParams *sp = static_cast<const ServerParams *>(s->params);
+    *launches = s->launches;
+    *gave_up = __atomic_load_n(sp->start_fails, __ATOMIC_ACQUIRE);
+    return IRGL_OK;
 }
 
 irgl_status irgl_batch_close(irgl_server s) {

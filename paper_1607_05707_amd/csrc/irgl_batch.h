@@ -200,6 +200,18 @@ __global__ __launch_bounds__(B) void batch_kernel(BatchParams bp) {
 // after idle_ticks without work, and after the gang barrier workgroup 0
 // decides for the whole grid whether to end (stop, or still no work) or go
 // on, so the grid always ends together.  Every wait is bounded (watchdog).
+//
+// Residency.  The barriers assume every workgroup of the grid is resident.
+// A cooperative launch sizes the grid for an otherwise idle device, but a
+// kernel on another stream (the caller's own work between requests) can
+// still hold part of it while the server's workgroups are dispatched; the
+// resident teams would then claim descriptors that can never be run.  So no
+// workgroup claims anything before all of them have checked in on the start
+// word.  If they are not all in within start_ticks, one CAS decides that the
+// launch gives up: every workgroup leaves at once, nothing is claimed, and
+// the host launches again while work is pending.  A descriptor claimed by a
+// team whose join barrier still fails (watchdog) is reported with the
+// watchdog status by its claimer, never left claimed and unreported.
 // ---------------------------------------------------------------------------
 struct ServerParams {
     BatchParams bp;                 // team layout and thresholds (bp.tasks unused)
@@ -210,8 +222,10 @@ struct ServerParams {
     uint32_t *done;                 // HOST pinned: per slot, (ticket + 1) when finished
     Stats *host_stats;              // HOST pinned: per slot statistics
     const uint32_t *stop;           // HOST pinned: stop request
+    uint32_t *start_fails;          // HOST pinned: launches that gave up at the start check
     uint32_t ring_cap;
     unsigned long long idle_ticks;
+    unsigned long long start_ticks; // deadline of the start check
 };
 
 // What the gang region holds after its control block: the claimed
@@ -219,10 +233,14 @@ struct ServerParams {
 struct GangInfo {
     TaskDesc desc;
     uint32_t ticket;
-    uint32_t kind;      // kGangTask or kGangExit
-    uint32_t decision;  // exit gang: 1 = end the launch
+    uint32_t kind;         // kGangTask or kGangExit
+    uint32_t decision;     // exit gang: 1 = end the launch
+    uint32_t start_count;  // workgroups checked in at the start of this launch
+    uint32_t start_state;  // 0 = checking in, 1 = all resident, 2 = launch gives up
     uint32_t pad;
 };
+constexpr uint32_t kStartGo = 1;
+constexpr uint32_t kStartGiveUp = 2;
 constexpr uint32_t kGangTask = 1;
 constexpr uint32_t kGangExit = 2;
 constexpr unsigned long long kPending = 1ull << 63;
@@ -284,7 +302,27 @@ __global__ __launch_bounds__(B) void server_kernel(ServerParams sp) {
     const bool leader = tm.id == 0 && threadIdx.x == 0;
     constexpr uint32_t kGang = 0xFFFFFFFEu;
     constexpr uint32_t kQuit = 0xFFFFFFFFu;
-    uint32_t joined = 0;  // gangs this team has joined (leader's copy)
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t joined = 0;         // gangs this team has joined (leader's copy)
+    uint32_t gang_claim = kNone;  // leader: ticket of the gang it claimed, until the gang starts
+    uint32_t task_claim = kNone;  // leader: ticket of the team task it claimed, until the task starts
+
+    // start check: every workgroup resident before anything is claimed
+    if (threadIdx.x == 0) {
+        if (atomicAdd(&gi->start_count, 1u) + 1u == gridDim.x) atomicCAS(&gi->start_state, 0u, kStartGo);
+        const unsigned long long t0 = wall_clock64();
+        uint32_t st;
+        while ((st = load_agent(&gi->start_state)) == 0u) {
+            if (wall_clock64() - t0 > sp.start_ticks) atomicCAS(&gi->start_state, 0u, kStartGiveUp);
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (st != kStartGo && blockIdx.x == 0)
+            __hip_atomic_store(sp.start_fails, load_sys(sp.start_fails) + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        sm.flag = st == kStartGo ? 1 : 0;
+    }
+    __syncthreads();
+    if (!sm.flag) return;  // uniform: the launch gave up before claiming anything
 
     for (;;) {
         if (leader) {
@@ -311,9 +349,11 @@ __global__ __launch_bounds__(B) void server_kernel(ServerParams sp) {
                             gi->ticket = h;
                             gi->kind = kGangTask;
                             joined = seq + 1;
+                            gang_claim = h;
                         } else {
                             copy_desc(mine, slot);
                             action = h;
+                            task_claim = h;
                         }
                         break;
                     }
@@ -337,14 +377,26 @@ __global__ __launch_bounds__(B) void server_kernel(ServerParams sp) {
             }
             store_agent(&bp.team_task[team_id], action);
         }
-        if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) return;
+        if (!grid_barrier(ctrl, bs, &sm.flag, nullptr, tm)) {
+            // the team cannot run what its leader claimed: report it failed
+            if (leader) {
+                if (task_claim != kNone) report_task(sp, *mine, task_claim, false);
+                if (gang_claim != kNone) report_task(sp, gi->desc, gang_claim, false);
+            }
+            return;
+        }
+        task_claim = kNone;  // the team has it: run_task's end reports it
         if (threadIdx.x == 0) s_ticket = load_agent(&bp.team_task[team_id]);
         __syncthreads();
         const uint32_t ticket = s_ticket;
         if (ticket == kQuit) return;  // uniform across the team
         if (ticket == kGang) {
             // every team is here: the gang region's descriptor and kind are visible
-            if (!grid_barrier(gctrl, gbs, &sm.flag, nullptr, grid)) return;
+            if (!grid_barrier(gctrl, gbs, &sm.flag, nullptr, grid)) {
+                if (leader && gang_claim != kNone) report_task(sp, gi->desc, gang_claim, false);
+                return;
+            }
+            gang_claim = kNone;  // started: workgroup 0 reports it
             if (gi->kind == kGangExit) {
                 if (grid.id == 0 && threadIdx.x == 0) {
                     const uint32_t h = static_cast<uint32_t>(

@@ -515,6 +515,8 @@ _lib.irgl_batch_poll.restype = ctypes.c_int32
 _lib.irgl_batch_poll.argtypes = [_c, ctypes.c_uint64, ctypes.POINTER(irgl_stats), ctypes.POINTER(ctypes.c_int32)]
 _lib.irgl_batch_close.restype = ctypes.c_int32
 _lib.irgl_batch_close.argtypes = [_c]
+_lib.irgl_batch_launches.restype = ctypes.c_int32
+_lib.irgl_batch_launches.argtypes = [_c, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
 
 
 def _graph_array(graphs):
@@ -598,6 +600,13 @@ def irgl_batch_poll(s: Server, ticket: int):
             task.stats = d
         return d
     return None
+
+
+def irgl_batch_launches(s: Server):
+    """(server kernel launches so far, launches that gave up at their start check)."""
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_lib.irgl_batch_launches(s.handle, ctypes.byref(a), ctypes.byref(b)), "irgl_batch_launches")
+    return int(a.value), int(b.value)
 
 
 def irgl_batch_close(s: Server) -> None:

@@ -43,7 +43,8 @@ def _wait(irgl, server, tickets, timeout=30.0):
                 st = irgl.irgl_batch_poll(server, t)
                 if st is not None:
                     out[t] = st
-        assert time.time() - t0 < timeout, "server did not finish"
+        assert time.time() - t0 < timeout, (f"server did not finish: {sorted(set(tickets) - set(out))} pending, "
+                                            f"(launches, gave up at start) = {irgl.irgl_batch_launches(server)}")
     return out
 
 
@@ -74,16 +75,18 @@ def test_server_results_match_oracle_and_alone(irgl, graphs):
     server.close()
 
 
-@pytest.mark.parametrize("gang_edges,team,gang_queue", [(20_000, 8, 0), (1, 4, 0), (20_000, 10_000, 0),
-                                                        (1 << 30, 8, 6)])
-def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team, gang_queue):
+@pytest.mark.parametrize("gang_edges,team,gang_queue,barrier", [(20_000, 8, 0, 0), (1, 4, 0, 0),
+                                                                (20_000, 10_000, 0, 0), (1 << 30, 8, 6, 0),
+                                                                (20_000, 8, 0, 1), (1, 4, 0, 1)])
+def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team, gang_queue, barrier):
     """Tasks on graphs with at least gang_edges edges (or enqueued while fewer
     than gang_queue are in flight) run on the whole grid between the teams'
     own tasks; every result equals the oracle, in ring order or not, and the
     kernel ends and relaunches between waves."""
-    print(f"[case] gang_edges={gang_edges} team={team} gang_queue={gang_queue}", flush=True)
+    print(f"[case] gang_edges={gang_edges} team={team} gang_queue={gang_queue} barrier={barrier}", flush=True)
     server = irgl.irgl_batch_open([hg for _, hg, _ in graphs],
-                                  cfg={"team": team, "gang_edges": gang_edges, "gang_queue": gang_queue},
+                                  cfg={"team": team, "gang_edges": gang_edges, "gang_queue": gang_queue,
+                                       "barrier": barrier},
                                   ring_cap=32, idle_ms=5)
     rng = np.random.default_rng(gang_edges + team)
     for wave in range(2):
@@ -103,7 +106,8 @@ def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team, gang_queue):
                         st = irgl.irgl_batch_poll(server, old)
                         if st is not None:
                             stats[old] = st
-                assert time.time() - t0 < 30.0
+                assert time.time() - t0 < 30.0, (sorted(set(tickets) - set(stats)),
+                                                  irgl.irgl_batch_launches(server))
             tasks.append((gi, t))
             tickets.append(tk)
         stats.update(_wait(irgl, server, [tk for tk in tickets if tk not in stats]))
@@ -119,6 +123,7 @@ def test_gang_tasks_in_the_mix(irgl, graphs, gang_edges, team, gang_queue):
             if t.parent is not None:
                 rp, col, w = np_g
                 oracle.validate(rp, col, t.src, got, t.parent.cpu().numpy(), None if t.kind == 0 else w)
+        print(f"[wave {wave}] (launches, gave up at start) = {irgl.irgl_batch_launches(server)}", flush=True)
         time.sleep(0.05)  # idle: the kernel ends, the next wave relaunches it
     server.close()
 
