@@ -168,8 +168,9 @@ def main() -> int:
     ap.add_argument("--t-bitmap", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--mode", default="persistent", choices=["persistent", "hostloop"])
-    ap.add_argument("--reorder", type=int, default=0, choices=[0, 1],
-                    help="1: upload through irgl_graph_upload_reordered (degree-sorted relabelling)")
+    ap.add_argument("--reorder", type=int, default=1, choices=[0, 1],
+                    help="1 (default): upload through irgl_graph_upload_reordered (degree-sorted "
+                         "relabelling, one-time, results under caller ids); 0: plain upload")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -206,7 +207,12 @@ def main() -> int:
     g = make_workload(args.workload, dev, args.sources)
     torch.cuda.synchronize()
     log(f"generated {g.name}: n={g.n} m={g.m} sources={len(g.sources)} in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     hg = irgl.upload(g, reorder=bool(args.reorder))
+    torch.cuda.synchronize()
+    upload_ms = 1e3 * (time.perf_counter() - t_up)
+    log(f"upload ({'degree-sorted relabelling' if args.reorder else 'caller ids'}): {upload_ms:.1f} ms (untimed)")
     cfg = {"block": args.block, "t_wave": args.t_wave, "t_block": args.t_block, "t_grid": args.t_grid,
            "t_bitmap": args.t_bitmap, "grid": args.grid,
            "mode": 1 if args.mode == "hostloop" else 0}
@@ -350,6 +356,7 @@ def main() -> int:
             "mode": args.mode,
             "block": args.block or "default",
             "upload": "degree-sorted relabelling" if args.reorder else "caller ids",
+            "upload_ms_untimed": round(upload_ms, 1),
         },
         "per_kind": {names[k]: {kk: vv for kk, vv in kind_summary[k].items() if kk != "total_ms"}
                      for k in kinds},

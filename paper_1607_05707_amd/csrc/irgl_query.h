@@ -207,60 +207,92 @@ __device__ __forceinline__ uint32_t next_threshold(uint32_t thresh, uint32_t far
 // top-down invocation has its worklist.
 // ---------------------------------------------------------------------------
 
+// Vertices per thread per step of the two full-vertex passes of a bottom-up
+// invocation: their loads are issued together (measured on RMAT-22: BFS
+// 0.543 ms against 0.583 ms with one vertex per step).
+constexpr int kPullV = 4;
+
 // Bitmaps for a bottom-up invocation at level `cur`: frontier = (level == cur),
-// visited = (level != INF).  One ballot pair per 64 consecutive vertices.
+// visited = (level != INF).  One ballot pair per 64 consecutive vertices;
+// thread t of a step handles vertices base + j * blockDim.x + t, j < kPullV.
 __device__ __forceinline__ void build_pull_bitmaps(const Params &p, uint32_t cur, Team tm) {
     const uint32_t n = static_cast<uint32_t>(p.n);
-    const uint32_t stride = tm.size * blockDim.x;
-    for (uint32_t base = tm.id * blockDim.x; base < n; base += stride) {
-        const uint32_t v = base + threadIdx.x;
-        const uint32_t lv = v < n ? p.val[v] : kInf;
-        const unsigned long long mv = __ballot(lv != kInf);
-        const unsigned long long mfr = __ballot(lv == cur);
-        const int lane = lane_id();
-        const uint32_t v0 = v - static_cast<uint32_t>(lane);
-        if (lane == 0 && v0 < n) {
-            p.visited[v0 >> 5] = static_cast<uint32_t>(mv);
-            p.frontier[v0 >> 5] = static_cast<uint32_t>(mfr);
+    const uint32_t step = blockDim.x * kPullV;
+    const int lane = lane_id();
+    for (uint32_t base = tm.id * step; base < n; base += tm.size * step) {
+        uint32_t lv[kPullV];
+#pragma unroll
+        for (int j = 0; j < kPullV; ++j) {
+            const uint32_t v = base + j * blockDim.x + threadIdx.x;
+            lv[j] = v < n ? p.val[v] : kInf;
         }
-        if (lane == 32 && v < n) {
-            p.visited[v >> 5] = static_cast<uint32_t>(mv >> 32);
-            p.frontier[v >> 5] = static_cast<uint32_t>(mfr >> 32);
+#pragma unroll
+        for (int j = 0; j < kPullV; ++j) {
+            const uint32_t v = base + j * blockDim.x + threadIdx.x;
+            const unsigned long long mv = __ballot(lv[j] != kInf);
+            const unsigned long long mfr = __ballot(lv[j] == cur);
+            const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
+            if (lane == 0 && v0 < n) {
+                p.visited[v0 >> 5] = static_cast<uint32_t>(mv);
+                p.frontier[v0 >> 5] = static_cast<uint32_t>(mfr);
+            }
+            if (lane == 32 && v < n) {
+                p.visited[v >> 5] = static_cast<uint32_t>(mv >> 32);
+                p.frontier[v >> 5] = static_cast<uint32_t>(mfr >> 32);
+            }
         }
     }
 }
 
+// The pull pass: every unvisited vertex scans its neighbours kUMax at a time
+// and stops at the first one in the frontier.  The visited words and row
+// offsets of a thread's kPullV vertices are loaded together first.
 template <int B>
 __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team tm, Pushers &pu,
                                            unsigned long long &scanned) {
     const uint32_t n = static_cast<uint32_t>(p.n);
-    for (uint32_t base = tm.id * B; base < n; base += tm.size * B) {
-        const uint32_t v = base + threadIdx.x;
-        int r0 = 0, r1 = 0;
-        if (v < n && !((p.visited[v >> 5] >> (v & 31)) & 1u)) {
-            r0 = p.row_ptr[v];
-            r1 = p.row_ptr[v + 1];
-        }
-        int found = -1;
-        for (int e0 = r0; e0 < r1; e0 += kUMax) {
-            int u[kUMax];
-            uint32_t fw[kUMax];
+    constexpr uint32_t kStep = B * kPullV;
+    for (uint32_t base = tm.id * kStep; base < n; base += tm.size * kStep) {
+        uint32_t vw[kPullV];
+        int rr0[kPullV], rr1[kPullV];
 #pragma unroll
-            for (int k = 0; k < kUMax; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
-#pragma unroll
-            for (int k = 0; k < kUMax; ++k) fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
-#pragma unroll
-            for (int k = 0; k < kUMax; ++k)
-                if (found < 0 && u[k] >= 0 && ((fw[k] >> (u[k] & 31)) & 1u)) found = u[k];
-            scanned += static_cast<unsigned long long>(min(kUMax, r1 - e0));
-            if (found >= 0) break;
+        for (int j = 0; j < kPullV; ++j) {
+            const uint32_t v = base + j * B + threadIdx.x;
+            vw[j] = v < n ? p.visited[v >> 5] : ~0u;
         }
-        if (found >= 0) {
-            p.val[v] = next;
-            if (p.parent) p.parent[v] = p.perm ? p.perm[found] : found;
-            pu.mf += static_cast<unsigned long long>(r1 - r0);
+#pragma unroll
+        for (int j = 0; j < kPullV; ++j) {
+            const uint32_t v = base + j * B + threadIdx.x;
+            const bool unvisited = v < n && !((vw[j] >> (v & 31)) & 1u);
+            rr0[j] = unvisited ? p.row_ptr[v] : 0;
+            rr1[j] = unvisited ? p.row_ptr[v + 1] : 0;
         }
-        pu.near(found >= 0, static_cast<int>(v));
+#pragma unroll
+        for (int j = 0; j < kPullV; ++j) {
+            const uint32_t v = base + j * B + threadIdx.x;
+            const int r0 = rr0[j], r1 = rr1[j];
+            int found = -1;
+            for (int e0 = r0; e0 < r1; e0 += kUMax) {
+                int u[kUMax];
+                uint32_t fw[kUMax];
+#pragma unroll
+                for (int k = 0; k < kUMax; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
+#pragma unroll
+                for (int k = 0; k < kUMax; ++k)
+                    fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
+#pragma unroll
+                for (int k = 0; k < kUMax; ++k)
+                    if (found < 0 && u[k] >= 0 && ((fw[k] >> (u[k] & 31)) & 1u)) found = u[k];
+                scanned += static_cast<unsigned long long>(min(kUMax, r1 - e0));
+                if (found >= 0) break;
+            }
+            if (found >= 0) {
+                p.val[v] = next;
+                if (p.parent) p.parent[v] = p.perm ? p.perm[found] : found;
+                pu.mf += static_cast<unsigned long long>(r1 - r0);
+            }
+            pu.near(found >= 0, static_cast<int>(v));
+        }
     }
 }
 
