@@ -242,7 +242,7 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
     const bool bitmap = c.t_bitmap != IRGL_BITMAP_NEVER || pull;
     L.frontier = L.visited + (bitmap ? bm : 0);
-    L.hub_v = L.frontier + (pull ? bm : 0);
+    L.hub_v = L.frontier + (pull ? 2 * bm : 0);  // current and next frontier bitmaps
     L.hub_cap = grid_list_cap(g->n, g->m, c.t_grid, c.block);
     L.hub_base = L.hub_v + align_up(static_cast<size_t>(L.hub_cap) * 4);
     // relabelled graph: values and parents under internal ids, scattered at the end
@@ -440,7 +440,9 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
     p.visited = (c.t_bitmap != IRGL_BITMAP_NEVER || pull) ? reinterpret_cast<uint32_t *>(base + L.visited)
                                                            : nullptr;
+    const size_t bm = align_up((static_cast<size_t>(g->n) + 31) / 32 * 4);
     p.frontier = pull ? reinterpret_cast<uint32_t *>(base + L.frontier) : nullptr;
+    p.frontier2 = pull ? reinterpret_cast<uint32_t *>(base + L.frontier + bm) : nullptr;
     p.do_alpha = c.do_alpha;
     p.do_beta = c.do_beta;
     p.m = g->m;

@@ -95,6 +95,7 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.far_tr = 0;
     p.refresh = 0;
     p.frontier = nullptr;  // batched BFS runs top-down
+    p.frontier2 = nullptr;
     p.do_alpha = 0;
     p.do_beta = 0;
     p.m = 0;

@@ -72,6 +72,7 @@ struct Params {
     uint32_t far_tr;      // host-loop mode: threshold raises so far
     uint32_t refresh;     // host-loop mode: refresh the bitmap in this invocation
     uint32_t *frontier;   // BFS bottom-up: bitmap of the current frontier, or null (top-down only)
+    uint32_t *frontier2;  // ... and of the next one (a bottom-up invocation writes it)
     uint32_t do_alpha;    // BFS direction choice (see irgl_config)
     uint32_t do_beta;
     long long m;          // edges of the graph

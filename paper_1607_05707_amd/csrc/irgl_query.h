@@ -212,10 +212,12 @@ __device__ __forceinline__ uint32_t next_threshold(uint32_t thresh, uint32_t far
 // 0.543 ms against 0.583 ms with one vertex per step).
 constexpr int kPullV = 4;
 
-// Bitmaps for a bottom-up invocation at level `cur`: frontier = (level == cur),
-// visited = (level != INF).  One ballot pair per 64 consecutive vertices;
-// thread t of a step handles vertices base + j * blockDim.x + t, j < kPullV.
-__device__ __forceinline__ void build_pull_bitmaps(const Params &p, uint32_t cur, Team tm) {
+// Bitmaps for a bottom-up invocation at level `cur` that follows a top-down
+// one: frontier = (level == cur), visited = (level != INF).  One ballot pair
+// per 64 consecutive vertices; thread t of a step handles vertices
+// base + j * blockDim.x + t, j < kPullV.  (After a bottom-up invocation the
+// pull pass itself leaves both bitmaps current.)
+__device__ __forceinline__ void build_pull_bitmaps(const Params &p, uint32_t cur, Team tm, uint32_t *frontier) {
     const uint32_t n = static_cast<uint32_t>(p.n);
     const uint32_t step = blockDim.x * kPullV;
     const int lane = lane_id();
@@ -234,22 +236,27 @@ __device__ __forceinline__ void build_pull_bitmaps(const Params &p, uint32_t cur
             const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
             if (lane == 0 && v0 < n) {
                 p.visited[v0 >> 5] = static_cast<uint32_t>(mv);
-                p.frontier[v0 >> 5] = static_cast<uint32_t>(mfr);
+                frontier[v0 >> 5] = static_cast<uint32_t>(mfr);
             }
             if (lane == 32 && v < n) {
                 p.visited[v >> 5] = static_cast<uint32_t>(mv >> 32);
-                p.frontier[v >> 5] = static_cast<uint32_t>(mfr >> 32);
+                frontier[v >> 5] = static_cast<uint32_t>(mfr >> 32);
             }
         }
     }
 }
 
 // The pull pass: every unvisited vertex scans its neighbours kUMax at a time
-// and stops at the first one in the frontier.  The visited words and row
-// offsets of a thread's kPullV vertices are loaded together first.
+// and stops at the first one in `frontier`.  The visited words and row
+// offsets of a thread's kPullV vertices are loaded together first.  The
+// vertices found form the next frontier: each wavefront writes their bits to
+// `next_frontier` and adds them to `visited` (the 64 vertices of a ballot
+// are consecutive and only their wavefront reads or writes those words in
+// this pass), so a following bottom-up invocation needs no rebuild.
 template <int B>
 __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team tm, Pushers &pu,
-                                           unsigned long long &scanned) {
+                                           unsigned long long &scanned, const uint32_t *frontier,
+                                           uint32_t *next_frontier) {
     const uint32_t n = static_cast<uint32_t>(p.n);
     constexpr uint32_t kStep = B * kPullV;
     for (uint32_t base = tm.id * kStep; base < n; base += tm.size * kStep) {
@@ -279,7 +286,7 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
                 for (int k = 0; k < kUMax; ++k) u[k] = e0 + k < r1 ? p.col[e0 + k] : -1;
 #pragma unroll
                 for (int k = 0; k < kUMax; ++k)
-                    fw[k] = u[k] >= 0 ? p.frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
+                    fw[k] = u[k] >= 0 ? frontier[static_cast<uint32_t>(u[k]) >> 5] : 0u;
 #pragma unroll
                 for (int k = 0; k < kUMax; ++k)
                     if (found < 0 && u[k] >= 0 && ((fw[k] >> (u[k] & 31)) & 1u)) found = u[k];
@@ -290,6 +297,17 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
                 p.val[v] = next;
                 if (p.parent) p.parent[v] = p.perm ? p.perm[found] : found;
                 pu.mf += static_cast<unsigned long long>(r1 - r0);
+            }
+            const unsigned long long mf = __ballot(found >= 0);
+            const int lane = lane_id();
+            const uint32_t v0 = v - static_cast<uint32_t>(lane);  // first vertex of this wavefront
+            if (lane == 0 && v0 < n) {
+                next_frontier[v0 >> 5] = static_cast<uint32_t>(mf);
+                p.visited[v0 >> 5] = vw[j] | static_cast<uint32_t>(mf);
+            }
+            if (lane == 32 && v < n) {
+                next_frontier[v >> 5] = static_cast<uint32_t>(mf >> 32);
+                p.visited[v >> 5] = vw[j] | static_cast<uint32_t>(mf >> 32);
             }
             pu.near(found >= 0, static_cast<int>(v));
         }
@@ -323,6 +341,8 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     // BFS direction choice (needs the frontier bitmap; symmetric graphs only)
     bool can_pull = !Op::kFar && p.frontier != nullptr;
     bool pull = false;
+    bool bitmaps_current = false;  // the previous invocation was bottom-up: its bitmaps describe this one
+    uint32_t *fr_cur = p.frontier, *fr_next = p.frontier2;
     unsigned long long m_seen = 0;  // out-degree sum of all worklists so far
     unsigned long long m_f = 0;     // out-degree sum of this invocation's worklist
     unsigned long long bu_seen = 0; // ctrl->bu_scan after the last bottom-up invocation
@@ -392,11 +412,17 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
                    }())) {
             // bottom-up invocation: bitmaps, barrier, pull
             pu.mf_out = &ctrl->mf[(it + 1) % 3];
-            build_pull_bitmaps(p, it, tm);
-            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            if (!bitmaps_current) {
+                build_pull_bitmaps(p, it, tm, fr_cur);
+                if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            }
             const unsigned long long edges_before = r.edges;
-            pull_level<B>(p, it + 1, tm, pu, r.edges);
-            refreshed = r.items;  // the visited bitmap was rebuilt for this invocation
+            pull_level<B>(p, it + 1, tm, pu, r.edges, fr_cur, fr_next);
+            uint32_t *const fr_t = fr_cur;
+            fr_cur = fr_next;
+            fr_next = fr_t;
+            bitmaps_current = true;
+            refreshed = r.items;  // the visited bitmap is exact again
             drain_all<B, Op>(pu, sm);
             add_block_total<B>(r.edges - edges_before, &ctrl->bu_scan);
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
@@ -413,6 +439,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             bu_seen = bu_now;
             if (tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
         } else {
+            bitmaps_current = false;  // top-down labels are not in the bitmaps
             pu.skf = far_sink(p, tr);
             pu.mf_out = &ctrl->mf[(it + 1) % 3];
             const unsigned long long edges_before = r.edges;
