@@ -143,10 +143,9 @@ def served_section(args, dev):
     queries = serve.query_stream(graphs, args.serve_queries, 5)
     arr = serve.poisson_arrivals(len(queries), args.serve_lambda * capacity, 12)
     cfg = autotune.load("serve")
-    lat_s, wall_s, _, rej = serve.run_served(graphs, queries, arr, 4 << 30, cfg={"team": cfg.get("team", 16),
-                                                                                  "block": cfg.get("block", 256)})
+    lat_s, wall_s, _, rej = serve.run_served(graphs, queries, arr, 4 << 30, cfg=cfg)
     lat_p, wall_p = serve.run_plain(graphs, queries, arr)
-    out = {"graphs": len(graphs), "queries": len(queries), "lambda_frac": args.serve_lambda,
+    out = {"graphs": len(graphs), "queries": len(queries), "lambda_frac": args.serve_lambda, "config": cfg,
            "plain_capacity_qps": round(capacity, 1), "budget_gb": 4, "rejected": rej,
            "served": serve.summarize(lat_s, wall_s), "plain": serve.summarize(lat_p, wall_p)}
     log(f"served {out['served']} plain {out['plain']}")

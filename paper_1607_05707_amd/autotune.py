@@ -1,11 +1,15 @@
-"""Autotuner for the batched launch.
+"""Autotuner for the batched launch and the open-batch server.
 
-Picks the workgroup size (from T_control, the sizes both loop bodies
-support), the team size and the grid-tier threshold by timing
-whole batches of a workload built from a HELD-OUT seed, one coordinate at a
-time, and caches the winner per device and workload class in a JSON file.
+batch: picks the workgroup size (from T_control, the sizes both loop bodies
+support), the team size and the grid-tier threshold by timing whole batches
+of a workload built from a HELD-OUT seed, one coordinate at a time.
+serve: picks the team size, the gang threshold and the gang queue depth by
+the p99 latency of a held-out Poisson query stream over the resident graph
+set at 80% of the plain capacity.  The winner is cached per device and
+workload class in a JSON file.
 
-  python -m paper_1607_05707_amd.autotune --workload batch --seed 257
+  python -m paper_1607_05707_amd.autotune --klass batch --seed 257
+  python -m paper_1607_05707_amd.autotune --klass serve --seed 7
 """
 from __future__ import annotations
 
@@ -24,6 +28,7 @@ from . import irgl
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 DEFAULT = {"block": 256, "team": 16, "t_grid": 0}
+SERVE_DEFAULT = {"block": 256, "team": 16, "gang_edges": 0, "gang_queue": 0}
 
 
 def batch_tasks(seed: int, count: int, device, rmat_scale: int = 20, rmat_sources: int = 64,
@@ -91,18 +96,56 @@ def tune(tasks, log=print):
     return cur, cur_t
 
 
+def tune_serve(graphs, queries, arrivals, log=print, ring_cap: int = 512):
+    """Coordinate search over the server configuration from SERVE_DEFAULT;
+    objective: p99 latency, then p50.  Returns (best config, its summary)."""
+    from . import serve
+    space = {
+        "team": [8, 16, 32, 64],
+        "gang_edges": [1 << 21, 1 << 22, 1 << 23, 1 << 24],
+        "gang_queue": [0, 4, 16],
+    }
+
+    def score(cfg):
+        lat, wall, _, rej = serve.run_served(graphs, queries, arrivals, 4 << 30, cfg=cfg, ring_cap=ring_cap)
+        if rej:
+            return (float("inf"), float("inf")), None
+        summ = serve.summarize(lat, wall)
+        return (summ["p99_ms"], summ["p50_ms"]), summ
+
+    cur = dict(SERVE_DEFAULT)
+    cur_s, cur_sum = score(cur)
+    log(f"[tune serve] start {cur} {cur_sum}")
+    for key, values in space.items():
+        for v in values:
+            if v == cur[key]:
+                continue
+            cand = dict(cur)
+            cand[key] = v
+            try:
+                s, summ = score(cand)
+            except irgl.IrglError:
+                continue
+            log(f"[tune serve] {cand} {summ}")
+            if s < cur_s:
+                cur, cur_s, cur_sum = cand, s, summ
+    return cur, cur_sum
+
+
 def cache_key(klass: str) -> str:
     name = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
     return f"{name}/{klass}"
 
 
 def load(klass: str):
-    """The cached best config for this device and workload class, else DEFAULT."""
+    """The cached best config for this device and workload class, else the
+    class default."""
+    default = SERVE_DEFAULT if klass == "serve" else DEFAULT
     try:
         with open(CACHE) as f:
-            return dict(json.load(f).get(cache_key(klass), DEFAULT))
+            return dict(json.load(f).get(cache_key(klass), default))
     except (OSError, ValueError):
-        return dict(DEFAULT)
+        return dict(default)
 
 
 def store(klass: str, cfg) -> None:
@@ -120,11 +163,23 @@ def store(klass: str, cfg) -> None:
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--seed", type=int, default=257, help="held-out seed (the bench measures seed 256)")
-    ap.add_argument("--count", type=int, default=256)
-    ap.add_argument("--klass", default="batch")
+    ap.add_argument("--seed", type=int, default=257,
+                    help="held-out seed (the bench measures batch seed 256, serve stream seed 5)")
+    ap.add_argument("--count", type=int, default=256, help="batch: tasks; serve: queries of the stream")
+    ap.add_argument("--klass", default="batch", choices=["batch", "serve"])
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
+    if args.klass == "serve":
+        from . import serve
+        graphs = serve.resident_set("full", dev)
+        capacity = serve.measure_capacity(graphs, serve.query_stream(graphs, 200, 6))
+        queries = serve.query_stream(graphs, args.count, args.seed)
+        arrivals = serve.poisson_arrivals(len(queries), 0.8 * capacity, args.seed + 1000)
+        best, summ = tune_serve(graphs, queries, arrivals, log=lambda s: print(s, file=sys.stderr, flush=True))
+        store("serve", best)
+        print(json.dumps({"class": "serve", "config": best, "summary": summ,
+                          "plain_capacity_qps": round(capacity, 1)}))
+        return 0
     keep, tasks = batch_tasks(args.seed, args.count, dev)
     best, t = tune(tasks, log=lambda s: print(s, file=sys.stderr, flush=True))
     store(args.klass, best)
