@@ -33,14 +33,20 @@ CSRC = os.path.join(HERE, "csrc")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+# The translation unit that defines and launches the profiled kernels: every
+# header under csrc/ and irgl.hip (other .hip / .cpp files, such as the
+# native runner, hold other kernels or the harness and do not change these).
+def digest_files():
+    return sorted(glob.glob(os.path.join(CSRC, "*.h"))) + [os.path.join(CSRC, "irgl.hip")]
+
+
 def source_digest() -> str:
-    """sha256 over the library's HIP sources (file names and contents)."""
+    """sha256 over the sources of the profiled kernels (file names and contents)."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if os.path.splitext(path)[1] in (".h", ".hip", ".cpp"):
-            h.update(os.path.basename(path).encode())
-            with open(path, "rb") as f:
-                h.update(f.read())
+    for path in digest_files():
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
