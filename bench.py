@@ -89,6 +89,50 @@ def cpu_baseline(g, sources, budget_s: float, gpu_results):
     }, parity
 
 
+def topology_section(args, hg, sources, kinds, cfg, mcc, stream):
+    """The same queries through the topology-driven Iterate (every invocation
+    visits all vertices, ReduceAndReturn Any(changed)): per-query time and
+    work against the data-driven loop, results compared bit for bit."""
+    dev = hg.row_ptr.device
+    tcfg = dict(cfg, mode=irgl.IRGL_MODE_TOPOLOGY)
+    out_d = torch.empty(hg.n, dtype=torch.int32, device=dev)
+    out_t = torch.empty(hg.n, dtype=torch.int32, device=dev)
+    stats = irgl.stats_tensor(dev)
+    fns = {0: irgl.irgl_bfs, 1: irgl.irgl_sssp}
+    res = {"sources": len(sources), "matches_data_driven": True}
+    for k in kinds:
+        ws_d = irgl.workspace(hg, k, False, cfg)
+        ws_t = irgl.workspace(hg, k, False, tcfg)
+        tot_ms, iters, edges, d_iters, d_edges = 0.0, 0, 0, 0, 0
+        for s in sources:
+            fns[k](hg, s, out_d, None, ws_d, stream, stats, cfg)
+            st = irgl.read_stats(stats)
+            d_iters += st["iterations"]
+            d_edges += st["edges"]
+            fns[k](hg, s, out_t, None, ws_t, stream, None, tcfg)  # warm
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fns[k](hg, s, out_t, None, ws_t, stream, stats, tcfg)
+            b.record(stream)
+            torch.cuda.synchronize()
+            tot_ms += a.elapsed_time(b)
+            st = irgl.read_stats(stats)
+            if st["status"] != 0:
+                raise SystemExit(f"topology-driven kind {k} from {s} failed: {irgl.irgl_status_string(st['status'])}")
+            iters += st["iterations"]
+            edges += st["edges"]
+            res["matches_data_driven"] &= bool(torch.equal(out_d, out_t))
+        nq = len(sources)
+        res[{0: "bfs", 1: "sssp"}[k]] = {
+            "avg_query_us": round(1e3 * tot_ms / nq, 1),
+            "gteps": round(sum(mcc[s] for s in sources) / (tot_ms / 1e3) / 1e9, 3),
+            "invocations": round(iters / nq, 1), "edges_scanned": int(edges / nq),
+            "data_driven_invocations": round(d_iters / nq, 1), "data_driven_edges_scanned": int(d_edges / nq)}
+    log(f"topology-driven {res}")
+    return res
+
+
 def batched_section(args, dev):
     """The batched workload (seed 256: uniform graphs of uneven size, BFS/SSSP
     alternating, plus R-MAT scale 20 with 64 BFS sources) in ONE persistent
@@ -174,6 +218,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-topology", action="store_true")
+    ap.add_argument("--topology-sources", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--serve-lambda", type=float, default=0.8)
@@ -319,6 +365,10 @@ def main() -> int:
         "kernel": f"{kname} (+ its init fill)",
     }
 
+    topology = None
+    if not args.no_topology:
+        topology = topology_section(args, hg, sources[:args.topology_sources], kinds, cfg, mcc, stream)
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -364,6 +414,7 @@ def main() -> int:
         "parity_vs_oracle": parity,
         "batched": batched,
         "served": served,
+        "topology": topology,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -80,10 +80,24 @@ enum {
     IRGL_MODE_PERSISTENT = 0, /* one cooperative launch; the Iterate loop runs on the
                                  device with a grid-wide barrier between invocations
                                  (iteration outlining, Section 4.3) */
-    IRGL_MODE_HOST_LOOP = 1   /* one launch per invocation, the host reads the worklist
+    IRGL_MODE_HOST_LOOP = 1,  /* one launch per invocation, the host reads the worklist
                                  size back after each (the un-outlined form); this mode
                                  synchronizes the stream once per level */
+    IRGL_MODE_TOPOLOGY = 2    /* topology-driven Iterate (Table 1: ForAll over every
+                                 node, ReduceAndReturn, Iterate While Any / Until All):
+                                 no worklists; every invocation visits all n vertices
+                                 (BFS expands those labelled in the previous invocation,
+                                 SSSP every reached one, Bellman-Ford) and returns
+                                 whether anything changed through a block-aggregated
+                                 reduction (see `reduce`); one cooperative launch.
+                                 Same results as the data-driven modes; stats.items
+                                 counts n per invocation */
 };
+
+/* ReduceAndReturn reductions of the topology-driven loop (Section 3). */
+#define IRGL_REDUCE_ANY 0u /* Iterate While Any(some vertex changed) */
+#define IRGL_REDUCE_ALL 1u /* Iterate Until All(no vertex changed): the same loop through
+                              the other reduction */
 
 /* A CSR graph: row_ptr int32[n+1] (monotone, row_ptr[0] = 0, row_ptr[n] = m),
  * col int32[m] (destinations in [0, n)), w uint32[m] (weights >= 1) or NULL.
@@ -169,6 +183,8 @@ typedef struct irgl_config {
                              IRGL_BARRIER_WORKGROUP for a launch whose workgroups are
                              not dealt round-robin to the XCDs.  Results do not
                              depend on it. */
+    uint32_t reduce;      /* IRGL_MODE_TOPOLOGY: IRGL_REDUCE_ANY (default) or
+                             IRGL_REDUCE_ALL; other values are IRGL_ERR_CONFIG */
 } irgl_config;
 
 /* Per-query statistics, written by the device when the query ends. */

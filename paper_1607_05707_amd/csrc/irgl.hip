@@ -156,6 +156,7 @@ struct Cfg {
     uint32_t delta;
     uint32_t do_alpha, do_beta;  // do_alpha == 0: no bottom-up invocations
     uint32_t barrier;
+    uint32_t reduce;  // topology-driven loop: IRGL_REDUCE_*
 };
 
 // Nested-parallelism thresholds (0 = default).  Vertices with t_grid or more
@@ -186,7 +187,10 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
     r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
-    if (r.mode != IRGL_MODE_PERSISTENT && r.mode != IRGL_MODE_HOST_LOOP) return IRGL_ERR_CONFIG;
+    if (r.mode != IRGL_MODE_PERSISTENT && r.mode != IRGL_MODE_HOST_LOOP && r.mode != IRGL_MODE_TOPOLOGY)
+        return IRGL_ERR_CONFIG;
+    r.reduce = c ? c->reduce : IRGL_REDUCE_ANY;
+    if (r.reduce != IRGL_REDUCE_ANY && r.reduce != IRGL_REDUCE_ALL) return IRGL_ERR_CONFIG;
     const uint32_t n = static_cast<uint32_t>(g->n);
     r.max_iter = (c && c->max_iter) ? c->max_iter : n + 1u;
     r.cap = (c && c->wl_capacity) ? std::min(c->wl_capacity, n) : n;
@@ -329,6 +333,16 @@ irgl_status launch_query(const irgl_graph_s *g, Params &p, const Cfg &c, hipStre
         if (st) return st;
         void *args[] = {&p};
         IRGL_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(persistent_kernel<B, Op>),
+                                            dim3(grid), dim3(B), args, 0, s));
+    } else if (c.mode == IRGL_MODE_TOPOLOGY) {
+        using TOp = typename TopoOf<Op>::type;
+        int grid = 0;
+        st = coresident_grid(topology_kernel<B, TOp>, B, g->device, c.grid, &grid);
+        if (st) return st;
+        p.reduce_all = c.reduce == IRGL_REDUCE_ALL ? 1u : 0u;
+        p.trace_len = 0;  // the per-invocation trace is recorded by the data-driven loop only
+        void *args[] = {&p};
+        IRGL_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(topology_kernel<B, TOp>),
                                             dim3(grid), dim3(B), args, 0, s));
     } else {
         int grid = c.grid;

@@ -41,7 +41,9 @@ struct alignas(128) Ctrl {
     unsigned long long bu_scan;
     // rotating worklist-tile counters (tiles taken beyond each workgroup's first)
     uint32_t tile[3];
-    uint32_t pad0[5];
+    // rotating ReduceAndReturn words of the topology-driven loop (one per invocation)
+    uint32_t red[3];
+    uint32_t pad0[2];
     // line 1: barrier generation (the only word waiting workgroups poll)
     uint32_t bar_gen;
     uint32_t pad1[31];

@@ -24,3 +24,4 @@
 #include "irgl_ops.h"
 #include "irgl_expand.h"
 #include "irgl_query.h"
+#include "irgl_topo.h"

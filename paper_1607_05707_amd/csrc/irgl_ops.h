@@ -76,6 +76,7 @@ struct Params {
     uint32_t do_alpha;    // BFS direction choice (see irgl_config)
     uint32_t do_beta;
     long long m;          // edges of the graph
+    uint32_t reduce_all;  // topology-driven loop: 1 = Iterate Until All(unchanged), 0 = While Any(changed)
 };
 
 // ---------------------------------------------------------------------------

@@ -41,6 +41,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
         c->cnt[2] = 0;
         for (int k = 0; k < 3; ++k) {
             c->tile[k] = 0;
+            c->red[k] = 0;
             c->hub[k] = 0;
             c->far_cnt[k] = 0;
             c->far_min[k] = kInf;

@@ -42,6 +42,9 @@ IRGL_SYMMETRIC = 1
 IRGL_VALIDATE = 2
 IRGL_MODE_PERSISTENT = 0
 IRGL_MODE_HOST_LOOP = 1
+IRGL_MODE_TOPOLOGY = 2
+IRGL_REDUCE_ANY = 0
+IRGL_REDUCE_ALL = 1
 IRGL_WATCHDOG_IMMEDIATE = 0xFFFFFFFF
 IRGL_BITMAP_NEVER = 0xFFFFFFFF
 IRGL_GRID_TIER_OFF = -1
@@ -67,7 +70,8 @@ class irgl_config(ctypes.Structure):
                 ("wl_capacity", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
                 ("abort_flag", ctypes.c_void_p), ("t_bitmap", ctypes.c_uint32),
                 ("trace_len", ctypes.c_uint32), ("do_alpha", ctypes.c_uint32), ("do_beta", ctypes.c_uint32),
-                ("delta", ctypes.c_uint32), ("trace", ctypes.c_void_p), ("barrier", ctypes.c_uint32)]
+                ("delta", ctypes.c_uint32), ("trace", ctypes.c_void_p), ("barrier", ctypes.c_uint32),
+                ("reduce", ctypes.c_uint32)]
 
 
 class irgl_stats(ctypes.Structure):

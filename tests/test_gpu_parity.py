@@ -227,6 +227,51 @@ def test_reordered_upload(irgl):
     assert e.value.status == irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
 
 
+@pytest.mark.parametrize("reduce", [0, 1])
+def test_topology_driven_iterate(irgl, reduce):
+    """IRGL_MODE_TOPOLOGY (a ForAll over every node whose invocation returns
+    ReduceAndReturn Any(changed), or All(unchanged), re-invoked While Any /
+    Until All): the oracle's levels and distances and valid parents on graphs
+    with hubs, a long-diameter grid, directed edges and a relabelled upload,
+    over block sizes and grid-tier settings.  BFS takes max level + 1
+    invocations and scans every edge of every reached vertex exactly once;
+    every invocation visits all n vertices."""
+    path = gg.from_edges(300, list(range(299)) + list(range(1, 300)), list(range(1, 300)) + list(range(299)),
+                         [1 + i % 7 for i in range(299)] * 2, name="path300")
+    cases = [(gg.rmat(12, seed=71, weight_seed=72, wmax=255), False),
+             (gg.config_road(width=64), False),
+             (gg.random_directed(2000, 16000, seed=73, weight_seed=74), False),
+             (gg.rmat(13, seed=75, weight_seed=76, wmax=255), True),
+             (path, False)]
+    for g0, reorder in cases:
+        g = _dev(g0)
+        hg = irgl.upload(g, reorder=reorder)
+        rp, col, w = g.numpy()
+        for src in gg.pick_sources(g, 2, seed=77):
+            for cfg in ({}, {"block": 512, "t_grid": -1}, {"block": 1024, "t_grid": 1024}):
+                c = dict(cfg, mode=irgl.IRGL_MODE_TOPOLOGY, reduce=reduce)
+                for kind in (BFS, SSSP):
+                    _say(f"topology {g.name} reorder={reorder} kind={kind} src={src} cfg={c}")
+                    out, par, st = irgl.query(hg, kind, src, with_parent=True, cfg=c)
+                    got = irgl.as_u32_numpy(out)
+                    ref = oracle.bfs(rp, col, src)[0] if kind == BFS else oracle.dijkstra(rp, col, w, src)[0]
+                    np.testing.assert_array_equal(got, ref, err_msg=f"{g.name} kind={kind} src={src} cfg={c}")
+                    oracle.validate(rp, col, src, got, par.cpu().numpy(), None if kind == BFS else w)
+                    assert st["status"] == 0
+                    assert st["items"] == g.n * st["iterations"]
+                    if kind == BFS:
+                        assert st["iterations"] == int(ref[ref != oracle.INF].max()) + 1
+                        assert st["edges"] == oracle.edges_scanned(rp, ref)
+    bad = irgl.irgl_config()
+    bad.mode = irgl.IRGL_MODE_TOPOLOGY
+    bad.reduce = 2
+    g = _dev(gg.config_grid64())
+    hg = irgl.upload(g)
+    with pytest.raises(irgl.IrglError) as e:
+        irgl.query(hg, BFS, 0, cfg=bad)
+    assert e.value.status == irgl.IRGL_ERR_CONFIG
+
+
 def test_road_grid_small(irgl):
     g = _dev(gg.config_road(width=256))
     hg = irgl.upload(g)
