@@ -93,6 +93,7 @@ def topology_section(args, hg, sources, kinds, cfg, mcc, stream):
     """The same queries through the topology-driven Iterate (every invocation
     visits all vertices, ReduceAndReturn Any(changed)): per-query time and
     work against the data-driven loop, results compared bit for bit."""
+    import torch
     from paper_1607_05707_amd import irgl
     dev = hg.row_ptr.device
     tcfg = dict(cfg, mode=irgl.IRGL_MODE_TOPOLOGY)
