@@ -7,6 +7,8 @@ HIP library and never calls it.
 * ``bfs`` / ``dijkstra``: serial C implementations (``oracle.c``) of the plain
   definitions the paper's worklist BFS (Section 4.1) converges to, and of
   textbook single-source shortest paths (the paper states only BFS).
+* ``kruskal``: the minimum spanning forest (serial Kruskal, ``oracle.c``) for
+  the Boruvka workload of the Atomic construct (Section 3).
 * ``floyd_warshall``: all-pairs min-plus closure in numpy, for tiny graphs.
 * ``validate``: the invariants that characterize exact distances plus a
   valid parent tree, vectorized over the CSR.
@@ -19,7 +21,7 @@ import os
 import numpy as np
 
 from .fw import floyd_warshall  # noqa: F401
-from .validate import validate, ValidationError  # noqa: F401
+from .validate import validate, validate_forest, ValidationError  # noqa: F401
 
 INF = 0xFFFFFFFF
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +44,9 @@ def _load():
         lib.oracle_dijkstra.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, u32p, i32p]
         lib.oracle_edges_scanned.restype = ctypes.c_int64
         lib.oracle_edges_scanned.argtypes = [ctypes.c_int32, i32p, u32p]
+        lib.oracle_kruskal.restype = ctypes.c_int64
+        lib.oracle_kruskal.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.POINTER(ctypes.c_uint8), i32p,
+                                       ctypes.POINTER(ctypes.c_int64)]
         _lib = lib
     return _lib
 
@@ -94,6 +99,27 @@ def edges_scanned(row_ptr, level) -> int:
     lv = np.ascontiguousarray(level, dtype=np.uint32)
     return int(_load().oracle_edges_scanned(rp.size - 1, _ptr(rp, ctypes.c_int32),
                                             _ptr(lv, ctypes.c_uint32)))
+
+
+def kruskal(row_ptr, col, w):
+    """Minimum spanning forest of a symmetric CSR under the total edge order
+    (w, u, v).  Returns (weight, in_forest uint8[m] with both directions of
+    every forest edge set, component int32[n] = smallest vertex id of the
+    vertex's tree, number of forest edges)."""
+    rp, c = _csr(row_ptr, col)
+    ww = np.ascontiguousarray(w).view(np.uint32) if np.asarray(w).dtype.itemsize == 4 else \
+        np.ascontiguousarray(w, dtype=np.uint32)
+    n = rp.size - 1
+    in_forest = np.empty(max(int(rp[-1]), 1), dtype=np.uint8)
+    comp = np.empty(n, dtype=np.int32)
+    edges = ctypes.c_int64()
+    r = _load().oracle_kruskal(n, _ptr(rp, ctypes.c_int32), _ptr(c, ctypes.c_int32), _ptr(ww, ctypes.c_uint32),
+                               _ptr(in_forest, ctypes.c_uint8), _ptr(comp, ctypes.c_int32), ctypes.byref(edges))
+    if r == -3:
+        raise ValueError("oracle_kruskal: the CSR is not symmetric (an edge lacks its equal-weight reverse)")
+    if r < 0:
+        raise ValueError("oracle_kruskal: invalid arguments")
+    return int(r), in_forest[:int(rp[-1])], comp, int(edges.value)
 
 
 def level_histogram(level) -> np.ndarray:

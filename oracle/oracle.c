@@ -15,10 +15,14 @@
  *   dist[v]  = least sum of uint32 weights (each >= 1) over directed paths
  *              src -> v, 0xFFFFFFFF when no path exists (textbook
  *              single-source shortest paths; the paper states only BFS).
- *
+  *
  * Algorithms: a FIFO-queue breadth-first search and a binary-heap Dijkstra
  * with lazy deletion and a 64-bit distance accumulator.  Both are serial and
  * deliberately plain.
+ *
+ * For the Boruvka workload (the Atomic construct's example, Section 3): the
+ * minimum spanning forest of a symmetric weighted CSR by Kruskal's algorithm
+ * under the total edge order (w, u, v), which makes the forest unique.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -158,4 +162,120 @@ int64_t oracle_edges_scanned(int32_t n, const int32_t *row_ptr, const uint32_t *
     for (int32_t v = 0; v < n; ++v)
         if (level[v] != ORACLE_INF) s += (int64_t)row_ptr[v + 1] - row_ptr[v];
     return s;
+}
+
+/* ---- minimum spanning forest ------------------------------------------- */
+/*
+ * Minimum spanning forest of an undirected graph stored as a symmetric CSR
+ * (each edge {u, v} appears as u -> v and v -> u with the same weight).
+ * Kruskal's algorithm, written out plainly: list every undirected edge once
+ * (as its u < v entry), sort the list by the total order (w, u, v) -- under a
+ * total order the minimum forest is unique, so edge sets can be compared --
+ * and take each edge whose endpoints are still in different trees of a
+ * union-find (path halving, union by size).  Self-loops never join two trees.
+ *
+ * in_forest: caller-owned uint8[m]; both stored directions of every forest
+ * edge are set to 1, the rest to 0.  component: caller-owned int32[n] or
+ * NULL; the smallest vertex id of the vertex's tree.  *edges = forest edges.
+ * Returns the forest weight, -1 on invalid arguments / allocation failure,
+ * -3 when an edge has no reverse entry of equal weight.
+ */
+typedef struct {
+    uint32_t w;
+    int32_t u, v;
+    int64_t e; /* index of the u -> v entry */
+} mst_edge;
+
+static int mst_edge_cmp(const void *a, const void *b) {
+    const mst_edge *x = (const mst_edge *)a, *y = (const mst_edge *)b;
+    if (x->w != y->w) return x->w < y->w ? -1 : 1;
+    if (x->u != y->u) return x->u < y->u ? -1 : 1;
+    if (x->v != y->v) return x->v < y->v ? -1 : 1;
+    return 0;
+}
+
+static int32_t uf_find(int32_t *parent, int32_t x) {
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+/* the entry v -> u of v's row with weight wt, or -1 */
+static int64_t reverse_entry(const int32_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t v,
+                             int32_t u, uint32_t wt) {
+    for (int64_t f = row_ptr[v]; f < row_ptr[v + 1]; ++f)
+        if (col[f] == u && w[f] == wt) return f;
+    return -1;
+}
+
+int64_t oracle_kruskal(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                       uint8_t *in_forest, int32_t *component, int64_t *edges) {
+    if (n <= 0 || !row_ptr || !col || !w || !in_forest || !edges) return -1;
+    const int64_t m = row_ptr[n];
+    int64_t cnt = 0;
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (u < col[e]) ++cnt;
+    mst_edge *list = (mst_edge *)malloc((size_t)(cnt > 0 ? cnt : 1) * sizeof(mst_edge));
+    int32_t *parent = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int32_t *size = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!list || !parent || !size) {
+        free(list);
+        free(parent);
+        free(size);
+        return -1;
+    }
+    int64_t k = 0;
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+            if (u < col[e]) {
+                list[k].w = w[e];
+                list[k].u = u;
+                list[k].v = col[e];
+                list[k].e = e;
+                ++k;
+            }
+    qsort(list, (size_t)cnt, sizeof(mst_edge), mst_edge_cmp);
+    for (int32_t v = 0; v < n; ++v) {
+        parent[v] = v;
+        size[v] = 1;
+    }
+    memset(in_forest, 0, (size_t)m);
+    int64_t total = 0, taken = 0, status = 0;
+    for (int64_t i = 0; i < cnt; ++i) {
+        const int64_t f = reverse_entry(row_ptr, col, w, list[i].v, list[i].u, list[i].w);
+        if (f < 0) {
+            status = -3;
+            break;
+        }
+        int32_t a = uf_find(parent, list[i].u), b = uf_find(parent, list[i].v);
+        if (a == b) continue;
+        if (size[a] < size[b]) {
+            int32_t t = a;
+            a = b;
+            b = t;
+        }
+        parent[b] = a;
+        size[a] += size[b];
+        in_forest[list[i].e] = 1;
+        in_forest[f] = 1;
+        total += list[i].w;
+        ++taken;
+    }
+    if (status == 0 && component) {
+        /* the smallest vertex id of each tree, through its root */
+        for (int32_t v = 0; v < n; ++v) size[v] = n;
+        for (int32_t v = 0; v < n; ++v) {
+            int32_t r = uf_find(parent, v);
+            if (v < size[r]) size[r] = v;
+        }
+        for (int32_t v = 0; v < n; ++v) component[v] = size[uf_find(parent, v)];
+    }
+    free(list);
+    free(parent);
+    free(size);
+    *edges = taken;
+    return status < 0 ? status : total;
 }
