@@ -392,6 +392,53 @@ irgl_status irgl_batch_launches(irgl_server s, uint64_t *launches, uint64_t *gav
 /* Stop the server kernel, wait for it and release the handle. */
 irgl_status irgl_batch_close(irgl_server s);
 
+/* ---------------------------------------------------------------------
+ * Minimum spanning forest by Boruvka's algorithm: the workload of the
+ * Atomic construct (Section 3, the find-minimum-cross-component-edge
+ * kernel, whose atomic section updates a component's lightest weight and
+ * its edge together).  Rounds of find-min-edge over the vertices that still
+ * have a cross-component edge, hooking, and pointer jumping run in one
+ * cooperative launch with the grid barrier between phases.  Edges are
+ * ordered by (weight, smaller endpoint, larger endpoint), so the forest is
+ * unique.  The graph must be symmetric (every edge stored in both
+ * directions with the same weight) with rows sorted by destination (as
+ * the library's generators and irgl_graph_upload produce them; unsorted
+ * rows are correct but slower); results refer to the caller's vertex ids
+ * and CSR entries, also for a relabelled upload.
+ * --------------------------------------------------------------------- */
+
+/* How the atomic section is compiled. */
+#define IRGL_LOCK_PACKED 0u /* the two words form one 64-bit key (weight << 32 | edge),
+                               updated by one 64-bit atomicMin (default) */
+#define IRGL_LOCK_SPIN 1u   /* Atomic, blocking: a compare-and-swap lock per component
+                               taken in a divergence-safe retry loop */
+#define IRGL_LOCK_TICKET 2u /* Atomic under a ticket lock per component */
+
+typedef struct irgl_mst_config {
+    int32_t block;        /* 256 (default), 512 or 1024 */
+    int32_t grid;         /* workgroups; 0 = co-resident limit */
+    uint32_t lock;        /* IRGL_LOCK_* */
+    uint32_t watchdog_ms; /* bound of every barrier and lock wait (default 20000) */
+    uint32_t barrier;     /* IRGL_BARRIER_* */
+} irgl_mst_config;
+
+/* Device workspace bytes of irgl_mst on graph g. */
+irgl_status irgl_mst_workspace_bytes(irgl_graph g, size_t *bytes);
+
+/* Minimum spanning forest of g (weights required).  weight: DEVICE uint64[1],
+ * the forest weight.  component: DEVICE int32[n] or NULL: the smallest vertex
+ * id of each vertex's tree.  in_forest: DEVICE uint8[m] or NULL: 1 for both
+ * stored directions of every forest edge, else 0.  ws: at least
+ * irgl_mst_workspace_bytes.  dstats (DEVICE, optional): iterations = rounds,
+ * items = worklist vertices summed over rounds, edges = CSR entries scanned,
+ * frontier_edges = forest edges.  Asynchronous on `stream`.  Errors:
+ * IRGL_ERR_NO_WEIGHTS, IRGL_ERR_CONFIG (block / lock / barrier),
+ * IRGL_ERR_TOO_LARGE (m >= 2^31), IRGL_ERR_WORKSPACE_TOO_SMALL; on the device
+ * (in dstats.status) IRGL_ERR_INVALID_GRAPH for an edge without its reverse,
+ * IRGL_ERR_WATCHDOG for a wait past the limit. */
+irgl_status irgl_mst(irgl_graph g, uint64_t *weight, int32_t *component, uint8_t *in_forest, void *ws,
+                     size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_mst_config *cfg);
+
 #ifdef __cplusplus
 }
 #endif

@@ -823,6 +823,25 @@ irgl_status reorder_layout(int32_t n, int64_t m, bool weighted, ReorderLayout *o
 
 }  // namespace
 
+// For the library's other translation units (the Boruvka workload): the
+// failure bookkeeping behind irgl_last_hip_error, and the caller's CSR of a
+// graph handle.
+namespace irgl_shared {
+irgl_status note_hip_failure(hipError_t e) { return hip_fail(e); }
+
+irgl_status caller_csr(const irgl_graph_s *g, int *device, irgl_csr *out) {
+    if (!g || !device || !out) return IRGL_ERR_INVALID_ARGUMENT;
+    *device = g->device;
+    out->n = g->n;
+    out->m = g->m;
+    out->row_ptr = g->orig_row_ptr;
+    out->col = g->orig_col;
+    out->w = g->orig_w;
+    out->flags = g->flags;
+    return IRGL_OK;
+}
+}  // namespace irgl_shared
+
 extern "C" {
 
 int irgl_version(void) { return IRGL_VERSION; }

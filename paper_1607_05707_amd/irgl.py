@@ -322,6 +322,77 @@ def irgl_query_status(ws: torch.Tensor, stream=None) -> dict:
     return st.as_dict()
 
 
+# ---------------------------------------------------------------------------
+# Minimum spanning forest (Boruvka, the Atomic construct's workload).
+# ---------------------------------------------------------------------------
+
+IRGL_LOCK_PACKED = 0
+IRGL_LOCK_SPIN = 1
+IRGL_LOCK_TICKET = 2
+
+
+class irgl_mst_config(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("lock", ctypes.c_uint32),
+                ("watchdog_ms", ctypes.c_uint32), ("barrier", ctypes.c_uint32)]
+
+
+_lib.irgl_mst_workspace_bytes.restype = ctypes.c_int32
+_lib.irgl_mst_workspace_bytes.argtypes = [_c, ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_mst.restype = ctypes.c_int32
+_lib.irgl_mst.argtypes = [_c, _c, _c, _c, _c, ctypes.c_size_t, _c, _c, ctypes.POINTER(irgl_mst_config)]
+
+
+def _mst_config(cfg):
+    if cfg is None or isinstance(cfg, irgl_mst_config):
+        return cfg
+    c = irgl_mst_config()
+    for k, v in dict(cfg).items():
+        setattr(c, k, int(v))
+    return c
+
+
+def irgl_mst_workspace_bytes(g: Graph) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.irgl_mst_workspace_bytes(g.handle, ctypes.byref(out)), "irgl_mst_workspace_bytes")
+    return int(out.value)
+
+
+def irgl_mst(g: Graph, weight: torch.Tensor, component: Optional[torch.Tensor] = None,
+             in_forest: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None,
+             stats: Optional[torch.Tensor] = None, cfg=None) -> None:
+    """Asynchronous minimum spanning forest on `stream`: weight is a device
+    int64/uint64 [1]; component a device int32 [n] or None; in_forest a device
+    uint8 [m] or None."""
+    if g.handle is None:
+        raise ValueError("graph handle was freed")
+    wp = _dev_ptr(weight, "weight", (torch.int64, getattr(torch, "uint64", torch.int64)), 1)
+    cp_ = _dev_ptr(component, "component", _I32, g.n)
+    fp = _dev_ptr(in_forest, "in_forest", (torch.uint8,), int(g.col.numel()))
+    if ws is None:
+        raise ValueError("a workspace tensor is required (see irgl_mst_workspace_bytes())")
+    sp = _dev_ptr(stats, "stats", (torch.uint8,), STATS_BYTES) if stats is not None else None
+    c = _mst_config(cfg)
+    _check(_lib.irgl_mst(g.handle, wp, cp_, fp, _dev_ptr(ws, "ws", (torch.uint8,)), ws.numel(),
+                         _stream_handle(stream), sp, ctypes.byref(c) if c is not None else None), "irgl_mst")
+
+
+def mst(g: Graph, cfg=None, stream=None):
+    """Run irgl_mst synchronously with fresh outputs: (weight, component, in_forest, stats)."""
+    dev = g.row_ptr.device
+    weight = torch.zeros(1, dtype=torch.int64, device=dev)
+    comp = torch.empty(g.n, dtype=torch.int32, device=dev)
+    in_forest = torch.empty(int(g.col.numel()), dtype=torch.uint8, device=dev)
+    ws = torch.empty(irgl_mst_workspace_bytes(g), dtype=torch.uint8, device=dev)
+    stats = stats_tensor(dev)
+    irgl_mst(g, weight, comp, in_forest, ws, stream, stats, cfg)
+    if stream is not None:
+        stream.synchronize()
+    st = read_stats(stats)
+    if st["status"] != IRGL_OK:
+        raise IrglError(st["status"], "device")
+    return int(weight.item()), comp, in_forest, st
+
+
 def stats_tensor(device) -> torch.Tensor:
     """A zeroed device buffer for one irgl_stats."""
     return torch.zeros(STATS_BYTES, dtype=torch.uint8, device=device)

@@ -96,6 +96,7 @@ def test_ctypes_layouts_match_the_header(tmp_path):
     import subprocess
     from paper_1607_05707_amd import irgl
     structs = {"irgl_csr": irgl.irgl_csr, "irgl_config": irgl.irgl_config, "irgl_stats": irgl.irgl_stats,
+               "irgl_mst_config": irgl.irgl_mst_config,
                "irgl_task": irgl.irgl_task, "irgl_batch_config": irgl.irgl_batch_config}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "irgl.h"', "int main(void) {"]
     for name, cls in structs.items():
