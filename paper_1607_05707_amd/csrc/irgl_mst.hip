@@ -204,26 +204,35 @@ __device__ __forceinline__ void offer(const MstParams &p, int c, unsigned long l
     uint32_t mine = 0;
     if (pending && ticket) mine = atomicAdd(&p.ticket[c], 1u);
     const unsigned long long t0 = wall_clock64();
-    while (pending) {
-        const bool held = ticket ? load_agent(&p.serving[c]) == mine : atomicCAS(&p.lock[c], 0u, 1u) == 0u;
-        if (held) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const uint32_t cw = load_agent(&p.minwt[c]);
-            const int32_t ce = static_cast<int32_t>(load_agent(reinterpret_cast<uint32_t *>(&p.minedge[c])));
-            if (wt < cw || (wt == cw && (ce < 0 || edge < ce))) {
-                store_agent(&p.minwt[c], wt);
-                store_agent(reinterpret_cast<uint32_t *>(&p.minedge[c]), static_cast<uint32_t>(edge));
+    // The loop leaves only when no lane of the wavefront is pending (a
+    // wave-uniform test at the top).  With a per-lane exit the compiler may
+    // legally move the section and its release after the loop, where a lane
+    // holding the lock waits, masked off, for lanes of its own wavefront
+    // that spin on that lock: the divergence deadlock the Atomic construct
+    // exists to avoid.  Here the section runs in the iteration that took the
+    // lock, before the next test.
+    for (;;) {
+        if (__ballot(pending) == 0ull) break;
+        if (pending) {
+            const bool held = ticket ? load_agent(&p.serving[c]) == mine : atomicCAS(&p.lock[c], 0u, 1u) == 0u;
+            if (held) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const uint32_t cw = load_agent(&p.minwt[c]);
+                const int32_t ce = static_cast<int32_t>(load_agent(reinterpret_cast<uint32_t *>(&p.minedge[c])));
+                if (wt < cw || (wt == cw && (ce < 0 || edge < ce))) {
+                    store_agent(&p.minwt[c], wt);
+                    store_agent(reinterpret_cast<uint32_t *>(&p.minedge[c]), static_cast<uint32_t>(edge));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (ticket) store_agent(&p.serving[c], mine + 1u);
+                else store_agent(&p.lock[c], 0u);
+                pending = false;
+            } else if (wall_clock64() - t0 > p.spin_ticks) {
+                set_error(p.ctrl, kErrWatchdog, true);
+                pending = false;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            if (ticket) store_agent(&p.serving[c], mine + 1u);
-            else store_agent(&p.lock[c], 0u);
-            pending = false;
-        } else if (wall_clock64() - t0 > p.spin_ticks) {
-            set_error(p.ctrl, kErrWatchdog, true);
-            pending = false;
-        } else {
-            __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_s_sleep(1);
     }
 }
 
