@@ -425,7 +425,7 @@ typedef struct irgl_mst_config {
 /* Device workspace bytes of irgl_mst on graph g. */
 irgl_status irgl_mst_workspace_bytes(irgl_graph g, size_t *bytes);
 
-/* Minimum spanning forest of g (weights required).  weight: DEVICE uint64[1],
+/* Minimum spanning forest of g (weights required unless g has no edges).  weight: DEVICE uint64[1],
  * the forest weight.  component: DEVICE int32[n] or NULL: the smallest vertex
  * id of each vertex's tree.  in_forest: DEVICE uint8[m] or NULL: 1 for both
  * stored directions of every forest edge, else 0.  ws: at least

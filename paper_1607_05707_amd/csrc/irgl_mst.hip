@@ -589,7 +589,7 @@ irgl_status irgl_mst(irgl_graph g, uint64_t *weight, int32_t *component, uint8_t
     irgl_status st = irgl_shared::caller_csr(g, &dev, &csr);
     if (st) return st;
     if (!weight || !ws) return IRGL_ERR_INVALID_ARGUMENT;
-    if (!csr.w) return IRGL_ERR_NO_WEIGHTS;
+    if (!csr.w && csr.m > 0) return IRGL_ERR_NO_WEIGHTS;  // an edgeless graph needs none
     const int block = (cfg && cfg->block) ? cfg->block : 256;
     if (block != 256 && block != 512 && block != 1024) return IRGL_ERR_CONFIG;
     const uint32_t kind = cfg ? cfg->lock : IRGL_LOCK_PACKED;
