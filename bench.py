@@ -135,6 +135,46 @@ def topology_section(args, hg, sources, kinds, cfg, mcc, stream):
     return res
 
 
+def mst_section(hg, stream):
+    """Boruvka minimum spanning forest of the same graph (the Atomic
+    construct's workload) with each compilation of its atomic section: time,
+    rounds, scanned entries; the three forests must be identical."""
+    import torch
+    from paper_1607_05707_amd import irgl
+    dev = hg.row_ptr.device
+    res = {"graph": "the bench graph (caller's labelling)", "identical_forests": True}
+    ws = torch.empty(irgl.irgl_mst_workspace_bytes(hg), dtype=torch.uint8, device=dev)
+    ref = None
+    for name, lock in (("packed", irgl.IRGL_LOCK_PACKED), ("spin", irgl.IRGL_LOCK_SPIN),
+                       ("ticket", irgl.IRGL_LOCK_TICKET)):
+        weight = torch.zeros(1, dtype=torch.int64, device=dev)
+        comp = torch.empty(hg.n, dtype=torch.int32, device=dev)
+        forest = torch.empty(int(hg.col.numel()), dtype=torch.uint8, device=dev)
+        stats = irgl.stats_tensor(dev)
+        cfg = {"lock": lock}
+        irgl.irgl_mst(hg, weight, comp, forest, ws, stream, stats, cfg)  # warm
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        irgl.irgl_mst(hg, weight, comp, forest, ws, stream, stats, cfg)
+        b.record(stream)
+        torch.cuda.synchronize()
+        st = irgl.read_stats(stats)
+        if st["status"] != 0:
+            raise SystemExit(f"mst ({name}) failed: {irgl.irgl_status_string(st['status'])}")
+        out = (int(weight.item()), comp.clone(), forest.clone())
+        if ref is None:
+            ref = out
+        else:
+            res["identical_forests"] &= out[0] == ref[0] and bool(torch.equal(out[1], ref[1])) and \
+                bool(torch.equal(out[2], ref[2]))
+        res[name] = {"ms": round(a.elapsed_time(b), 3), "rounds": st["iterations"], "edges_scanned": st["edges"]}
+    res["weight"] = ref[0]
+    res["forest_edges"] = int(ref[2].sum().item()) // 2
+    log(f"mst {res}")
+    return res
+
+
 def batched_section(args, dev):
     """The batched workload (seed 256: uniform graphs of uneven size, BFS/SSSP
     alternating, plus R-MAT scale 20 with 64 BFS sources) in ONE persistent
@@ -221,6 +261,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-topology", action="store_true")
+    ap.add_argument("--no-mst", action="store_true")
     ap.add_argument("--topology-sources", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-queries", type=int, default=1000)
@@ -367,6 +408,10 @@ def main() -> int:
         "kernel": f"{kname} (+ its init fill)",
     }
 
+    mst = None
+    if not args.no_mst:
+        mst = mst_section(hg, stream)
+
     topology = None
     if not args.no_topology:
         topology = topology_section(args, hg, sources[:args.topology_sources], kinds, cfg, mcc, stream)
@@ -417,6 +462,7 @@ def main() -> int:
         "batched": batched,
         "served": served,
         "topology": topology,
+        "mst": mst,
     }
     print(json.dumps(line), flush=True)
     return 0
