@@ -33,6 +33,10 @@
 //   ticket  - the same section under a ticket lock.
 // Before taking a lock a lane reads the component's weight: weights only
 // fall during phase 1, so a candidate heavier than a stale read cannot win.
+// The lanes of a wavefront that offer to the same component first reduce
+// their candidates to one (cooperative conversion, Sections 3.5 and 4.2,
+// applied to the atomic section), so a giant component sees one lock
+// acquisition or atomic per wavefront instead of one per vertex.
 // Every lock wait is bounded by a wall-clock limit (IRGL_ERR_WATCHDOG).
 #include <hip/hip_runtime.h>
 
@@ -52,7 +56,6 @@ namespace irgl {
 namespace mst {
 
 constexpr unsigned long long kNoKey = ~0ull;
-constexpr int kTWave = 64;      // vertices with this many edges or more: one wavefront scans the row
 constexpr int kTBlock = 4096;   // ... this many or more: the whole workgroup
 constexpr int kMstQueue = 256;  // LDS push staging per wavefront
 
@@ -98,49 +101,40 @@ struct MstSmem {
     int flag;
     int owner;
     int big_v, big_r0, big_r1;
-    unsigned long long red_k1[NW];
-    int red_hi[NW];
-    int red_e[NW];
+    unsigned long long red[NW];
     unsigned long long wsum[NW];
+    int dsum[NW];
+    // gather tier: the workgroup's rows concatenated (exclusive scan of the
+    // degrees), each slot's owner found by a binary search
+    int gstart[B];
+    int gr0[B];
+    int gv[B];
+    int gc[B];
+    unsigned long long vmin[B];  // per row: lightest cross edge as (w << 32 | neighbour)
 };
 
-// Best edge of a scan: (k1 = w << 32 | lo, hi) in lexicographic order, and
-// the entry of the scanned row that holds it.
-struct Best {
-    unsigned long long k1;
-    int32_t hi;
-    int32_t e;
-};
+// For a fixed vertex v, ordering its edges {v, u} by (w, smaller endpoint,
+// larger endpoint) is ordering them by (w, u): an edge to u < v has the
+// smaller endpoint u < v, an edge to u > v has v.  So a row's lightest cross
+// edge is the minimum of the 64-bit row key w << 32 | u.
 
-__device__ __forceinline__ bool better(const Best &a, const Best &b) {
-    return a.k1 < b.k1 || (a.k1 == b.k1 && a.hi < b.hi);
-}
-
-// Scan entries [r0, r1) of vertex v (in steps of `step` from `first`) for
-// the lightest edge to another component.
-__device__ __forceinline__ Best scan_row(const MstParams &p, int v, int c, int r0, int r1, int first, int step,
-                                         unsigned long long &scanned) {
-    Best b{kNoKey, 0x7FFFFFFF, -1};
+// Row key minimum of entries [r0, r1) of vertex v in component c, entries
+// first, first + step, ...
+__device__ __forceinline__ unsigned long long scan_row(const MstParams &p, int v, int c, int r0, int r1, int first,
+                                                       int step, unsigned long long &scanned) {
+    unsigned long long b = kNoKey;
     for (int e = r0 + first; e < r1; e += step) {
         const int u = p.col[e];
         ++scanned;
         if (u == v || p.comp[u] == c) continue;
-        const int lo = min(u, v), hi = max(u, v);
-        const Best cand{(static_cast<unsigned long long>(p.w[e]) << 32) | static_cast<uint32_t>(lo), hi, e};
-        if (better(cand, b)) b = cand;
+        b = min(b, (static_cast<unsigned long long>(p.w[e]) << 32) | static_cast<uint32_t>(u));
     }
     return b;
 }
 
-__device__ __forceinline__ Best wave_min(Best b) {
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long b) {
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        Best o;
-        o.k1 = __shfl_xor(b.k1, off, kWave);
-        o.hi = __shfl_xor(b.hi, off, kWave);
-        o.e = __shfl_xor(b.e, off, kWave);
-        if (better(o, b)) b = o;
-    }
+    for (int off = kWave / 2; off > 0; off >>= 1) b = min(b, static_cast<unsigned long long>(__shfl_xor(b, off, kWave)));
     return b;
 }
 
@@ -171,21 +165,17 @@ __device__ __forceinline__ int row_of(const MstParams &p, int e) {
     return a;
 }
 
-// Candidate key (weight << 32 | canonical entry) of the best edge of vertex
-// v, or kNoKey.  Needs the entry of the other direction when v is the
-// larger endpoint.
-__device__ __forceinline__ unsigned long long candidate_key(const MstParams &p, int v, const Best &b) {
-    if (b.e < 0) return kNoKey;
-    const int u = p.col[b.e];
-    int canon = b.e;
-    if (u < v) {
-        canon = find_entry(p, u, v);
-        if (canon < 0) {  // no reverse entry: the CSR is not symmetric
-            set_error(p.ctrl, IRGL_ERR_INVALID_GRAPH, false);
-            return kNoKey;
-        }
+// Candidate key (weight << 32 | canonical entry) of row key rk of vertex v,
+// or kNoKey.  The canonical entry is the smaller endpoint's entry.
+__device__ __forceinline__ unsigned long long candidate_key(const MstParams &p, int v, unsigned long long rk) {
+    if (rk == kNoKey) return kNoKey;
+    const int u = static_cast<int>(rk & 0xFFFFFFFFull);
+    const int canon = find_entry(p, min(u, v), max(u, v));
+    if (canon < 0) {  // no reverse entry: the CSR is not symmetric
+        set_error(p.ctrl, IRGL_ERR_INVALID_GRAPH, false);
+        return kNoKey;
     }
-    return (b.k1 & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(canon);
+    return (rk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(canon);
 }
 
 // The atomic section of find-min-edge: make `k` the candidate of component
@@ -258,7 +248,10 @@ __device__ __forceinline__ unsigned long long block_sum(MstSmem<B> &sm, unsigned
 }
 
 // Phase 1 over worklist `in` (identity when null) of cnt_in vertices; pushes
-// the vertices that have a cross edge.
+// the vertices that have a cross edge.  Rows of kTBlock or more entries are
+// scanned by the whole workgroup one at a time; the other rows of a tile are
+// concatenated and dealt to the lanes in full rounds (load-balanced gather),
+// each slot folding its edge into its row's minimum with an LDS atomicMin.
 template <int B>
 __device__ __forceinline__ void find_min_edges(const MstParams &p, MstSmem<B> &sm, Team tm, const int32_t *in,
                                                uint32_t cnt_in, WaveQueue<kMstQueue> &wq, uint32_t *cnt_out,
@@ -275,8 +268,8 @@ __device__ __forceinline__ void find_min_edges(const MstParams &p, MstSmem<B> &s
             r1 = p.row_ptr[v + 1];
         }
         int deg = r1 - r0;
-        Best mine{kNoKey, 0x7FFFFFFF, -1};
-        // workgroup tier: the whole workgroup scans one large row at a time
+        unsigned long long rk = kNoKey;
+        // workgroup tier: one large row at a time
         while (__syncthreads_or(deg >= kTBlock)) {
             if (deg >= kTBlock) sm.owner = tid;
             __syncthreads();
@@ -288,41 +281,67 @@ __device__ __forceinline__ void find_min_edges(const MstParams &p, MstSmem<B> &s
             }
             __syncthreads();
             const int bv = sm.big_v;
-            Best b = wave_min(scan_row(p, bv, p.comp[bv], sm.big_r0, sm.big_r1, tid, B, scanned));
-            if (lane == 0) {
-                sm.red_k1[wid] = b.k1;
-                sm.red_hi[wid] = b.hi;
-                sm.red_e[wid] = b.e;
-            }
+            const unsigned long long b = wave_min(scan_row(p, bv, p.comp[bv], sm.big_r0, sm.big_r1, tid, B, scanned));
+            if (lane == 0) sm.red[wid] = b;
             __syncthreads();
             if (sm.owner == tid) {
-                for (int k = 0; k < NW; ++k) {
-                    const Best o{sm.red_k1[k], sm.red_hi[k], sm.red_e[k]};
-                    if (better(o, mine)) mine = o;
-                }
+                for (int k = 0; k < NW; ++k) rk = min(rk, sm.red[k]);
             }
             __syncthreads();
         }
-        // wavefront tier: one wavefront scans one medium row at a time
-        for (;;) {
-            const unsigned long long m = __ballot(deg >= kTWave);
-            if (m == 0ull) break;
-            const int leader = __ffsll(static_cast<long long>(m)) - 1;
-            const int lv = __shfl(v, leader, kWave);
-            const int lc = __shfl(c, leader, kWave);
-            const int l0 = __shfl(r0, leader, kWave);
-            const int l1 = __shfl(r1, leader, kWave);
-            const Best b = wave_min(scan_row(p, lv, lc, l0, l1, lane, kWave, scanned));
-            if (lane == leader) {
-                mine = b;
-                deg = 0;
+        // gather tier
+        const int incl = wave_inclusive_scan(deg);
+        if (lane == kWave - 1) sm.dsum[wid] = incl;
+        sm.vmin[tid] = kNoKey;
+        __syncthreads();
+        int total = 0, wpre = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            wpre += (k < wid) ? sm.dsum[k] : 0;
+            total += sm.dsum[k];
+        }
+        sm.gstart[tid] = wpre + incl - deg;
+        sm.gr0[tid] = r0;
+        sm.gv[tid] = v;
+        sm.gc[tid] = c;
+        __syncthreads();
+        for (int done = 0; done < total; done += B) {
+            const int slot = done + tid;
+            if (slot < total) {
+                int o = 0;
+#pragma unroll
+                for (int step = B / 2; step > 0; step >>= 1)
+                    if (sm.gstart[o + step] <= slot) o += step;
+                const int e = sm.gr0[o] + (slot - sm.gstart[o]);
+                const int u = p.col[e];
+                ++scanned;
+                if (u != sm.gv[o] && p.comp[u] != sm.gc[o])
+                    atomicMin(&sm.vmin[o], (static_cast<unsigned long long>(p.w[e]) << 32) | static_cast<uint32_t>(u));
             }
         }
-        // thread tier: the remaining short rows, one per lane
-        if (deg > 0) mine = scan_row(p, v, c, r0, r1, 0, 1, scanned);
-        const unsigned long long k = v >= 0 ? candidate_key(p, v, mine) : kNoKey;
-        offer(p, c, k, k != kNoKey);
-        wq.push(k != kNoKey, v, cnt_out, out, static_cast<uint32_t>(p.n), p.ctrl);
+        __syncthreads();
+        if (deg > 0) rk = sm.vmin[tid];
+        unsigned long long k = v >= 0 ? candidate_key(p, v, rk) : kNoKey;
+        const bool has = k != kNoKey;
+        // Cooperative conversion of the atomic section: the candidates of the
+        // wavefront's lanes that share the first candidate lane's component
+        // (in later rounds most lanes are in one giant component) are reduced
+        // to their minimum, and only that lane enters the section for them.
+        bool want = has;
+        const unsigned long long cm = __ballot(has);
+        if (cm) {
+            const int leader = __ffsll(static_cast<long long>(cm)) - 1;
+            const int cl = __shfl(c, leader, kWave);
+            const bool same = has && c == cl;
+            const unsigned long long kk = wave_min(same ? k : kNoKey);
+            if (same) {
+                want = lane == leader;
+                k = kk;
+            }
+        }
+        offer(p, c, k, want);
+        wq.push(has, v, cnt_out, out, static_cast<uint32_t>(p.n), p.ctrl);
+        __syncthreads();  // the gather arrays are rewritten by the next tile
     }
 }
 
@@ -357,21 +376,32 @@ __global__ __launch_bounds__(B) void mst_kernel(MstParams p) {
         find_min_edges<B>(p, sm, tm, in, cnt_in, wq, &ctrl->cnt[(round + 1) % 3], out, scanned);
         block_drain<B, kMstQueue>(wq, sm.fill, &sm.base, &ctrl->cnt[(round + 1) % 3], out, n, ctrl);
         if (!(ok = grid_barrier(ctrl, bs, &sm.flag, nullptr, tm))) break;
-        // phase 2: hook every root with a candidate, emit its edge
-        for (uint32_t c = gid; c < n; c += stride) {
-            if (p.comp[c] != static_cast<int32_t>(c)) continue;
-            const unsigned long long k = chosen(p, static_cast<int>(c));
-            if (k == kNoKey) continue;
-            const int e = static_cast<int>(k & 0xFFFFFFFFull);
-            const int lo = row_of(p, e), hi = p.col[e];
-            const int other = p.comp[lo] == static_cast<int32_t>(c) ? hi : lo;
-            const int c2 = p.comp[other];
-            const bool mutual = chosen(p, c2) == k;
-            p.hook[c] = (mutual && static_cast<int>(c) < c2) ? static_cast<int32_t>(c) : c2;
-            if (!(mutual && static_cast<int>(c) > c2)) {
-                const unsigned long long slot = atomicAdd(forest_count(ctrl), 1ull);
-                if (slot < n) p.forest[slot] = e;
-                added += static_cast<unsigned long long>(k >> 32);
+        // phase 2: hook every root with a candidate, emit its edge (the
+        // wavefront reserves its forest slots with one atomic)
+        for (uint32_t base2 = tm.id * B; base2 < n; base2 += stride) {
+            const uint32_t c = base2 + threadIdx.x;
+            bool emit = false;
+            int e = 0;
+            if (c < n && p.comp[c] == static_cast<int32_t>(c)) {
+                const unsigned long long k = chosen(p, static_cast<int>(c));
+                if (k != kNoKey) {
+                    e = static_cast<int>(k & 0xFFFFFFFFull);
+                    const int lo = row_of(p, e), hi = p.col[e];
+                    const int other = p.comp[lo] == static_cast<int32_t>(c) ? hi : lo;
+                    const int c2 = p.comp[other];
+                    const bool mutual = chosen(p, c2) == k;
+                    p.hook[c] = (mutual && static_cast<int>(c) < c2) ? static_cast<int32_t>(c) : c2;
+                    emit = !(mutual && static_cast<int>(c) > c2);
+                    if (emit) added += static_cast<unsigned long long>(k >> 32);
+                }
+            }
+            const unsigned long long em = __ballot(emit);
+            if (em) {
+                unsigned long long slot0 = 0;
+                if (lane_id() == 0) slot0 = atomicAdd(forest_count(ctrl), static_cast<unsigned long long>(__popcll(em)));
+                slot0 = __shfl(slot0, 0, kWave);
+                const unsigned long long slot = slot0 + lane_rank(em);
+                if (emit && slot < n) p.forest[slot] = e;
             }
         }
         if (!(ok = grid_barrier(ctrl, bs, &sm.flag, nullptr, tm))) break;
@@ -433,7 +463,21 @@ __global__ __launch_bounds__(B) void mst_kernel(MstParams p) {
     if (ok) ok = grid_barrier(ctrl, bs, &sm.flag, nullptr, tm);
     if (ok) {
         // smallest vertex id of every tree, then the per-entry marks
-        for (uint32_t v = gid; v < n; v += stride) atomicMin(&p.repmin[p.comp[v]], static_cast<int32_t>(v));
+        // (consecutive lanes hold consecutive ids: the first lane of each run
+        // of one component holds its smallest id in the wavefront)
+        for (uint32_t base3 = tm.id * B; base3 < n; base3 += stride) {
+            const uint32_t v = base3 + threadIdx.x;
+            const bool live = v < n;
+            const int cv = live ? p.comp[v] : -1;
+            const unsigned long long lm = __ballot(live);
+            bool mine = live;
+            if (lm) {
+                const int leader = __ffsll(static_cast<long long>(lm)) - 1;
+                const int cl = __shfl(cv, leader, kWave);
+                if (live && cv == cl && lane_id() != leader) mine = false;
+            }
+            if (mine) atomicMin(&p.repmin[cv], static_cast<int32_t>(v));
+        }
         const unsigned long long nf = min(__hip_atomic_load(forest_count(ctrl), __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT),
                                           static_cast<unsigned long long>(n));
