@@ -272,9 +272,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(queries shard by replication across GPUs; see the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(batched and served queries would shard by replicating the graphs and "
+              "routing each query to one GPU). Run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
