@@ -314,6 +314,7 @@ def main() -> int:
 
     # per-source numerator m_cc and reached count from one BFS each (untimed)
     mcc, reached, gpu_results = {}, {}, {}
+    blocks = {}  # workgroup size each kind resolved to
     n_check = min(len(sources), 2)
     for i, s in enumerate(sources):
         irgl.irgl_bfs(hg, s, out, None, ws[kinds[0]] if 0 in ws else irgl.workspace(hg, 0), stream,
@@ -323,12 +324,14 @@ def main() -> int:
             raise SystemExit(f"BFS from {s} failed: {irgl.irgl_status_string(st['status'])}")
         mcc[s] = st["frontier_edges"]
         reached[s] = st["items"]
+        blocks[0] = st["block"]
         if i < n_check:
             lv = irgl.as_u32_numpy(out).copy()
             d = None
             if 1 in kinds:
                 irgl.irgl_sssp(hg, s, out, None, ws[1], stream, stats, cfg)
                 d = irgl.as_u32_numpy(out).copy()
+                blocks[1] = irgl.read_stats(stats)["block"]
             gpu_results[s] = (lv, d)
     log(f"m_cc: mean {sum(mcc.values()) / len(mcc):.0f} over {len(mcc)} sources")
 
@@ -388,7 +391,7 @@ def main() -> int:
         }
     dom = max(kinds, key=lambda k: kind_summary[k]["total_ms"])
     ks = kind_summary[dom]
-    kname = f"persistent_kernel<{args.block or 256}, irgl::{['BfsOp', 'SsspOp'][dom]}>"
+    kname = f"persistent_kernel<{blocks[dom]}, irgl::{['BfsOp', 'SsspOp'][dom]}>"
     # measured HBM bytes per launch of that kernel (rocprofv3 FETCH_SIZE +
     # WRITE_SIZE, scaled by a plain copy), only while the HIP sources are the
     # ones the counters were taken on
@@ -450,7 +453,7 @@ def main() -> int:
             "sources": len(sources),
             "queries_per_step": len(sources) * len(kinds),
             "mode": args.mode,
-            "block": args.block or "default",
+            "block": {names[k]: blocks[k] for k in kinds},
             "upload": "degree-sorted relabelling" if args.reorder else "caller ids",
             "upload_ms_untimed": round(upload_ms, 1),
         },

@@ -124,7 +124,8 @@ typedef struct irgl_graph_s *irgl_graph;
  * the grid and gather tiers are used; the workgroup and wavefront tiers take
  * ranges when their thresholds are set. */
 typedef struct irgl_config {
-    int32_t block;        /* threads per workgroup: 256 (default), 512 or 1024 */
+    int32_t block;        /* threads per workgroup: 256, 512 or 1024 (default: 1024
+                             for BFS, 512 for SSSP) */
     int32_t t_wave;       /* wavefront tier threshold, >= 1 (default: t_block, or 64
                              when t_block is set) */
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default: t_grid) */
@@ -415,7 +416,7 @@ irgl_status irgl_batch_close(irgl_server s);
 #define IRGL_LOCK_TICKET 2u /* Atomic under a ticket lock per component */
 
 typedef struct irgl_mst_config {
-    int32_t block;        /* 256 (default), 512 or 1024 */
+    int32_t block;        /* 256, 512 (default) or 1024 */
     int32_t grid;         /* workgroups; 0 = co-resident limit */
     uint32_t lock;        /* IRGL_LOCK_* */
     uint32_t watchdog_ms; /* bound of every barrier and lock wait (default 20000) */

@@ -3,9 +3,9 @@
 batch: picks the workgroup size (from T_control, the sizes both loop bodies
 support), the team size and the grid-tier threshold by timing whole batches
 of a workload built from a HELD-OUT seed, one coordinate at a time.
-serve: picks the team size, the gang threshold and the gang queue depth by
-the p99 latency of a held-out Poisson query stream over the resident graph
-set at 80% of the plain capacity.  The winner is cached per device and
+serve: picks the workgroup size, the team size, the gang threshold and the
+gang queue depth by the p99 latency of a held-out Poisson query stream over
+the resident graph set at 80% of the plain capacity.  The winner is cached per device and
 workload class in a JSON file.
 
   python -m paper_1607_05707_amd.autotune --klass batch --seed 257
@@ -101,6 +101,7 @@ def tune_serve(graphs, queries, arrivals, log=print, ring_cap: int = 512):
     objective: p99 latency, then p50.  Returns (best config, its summary)."""
     from . import serve
     space = {
+        "block": [256, 512, 1024],
         "team": [8, 16, 32, 64],
         "gang_edges": [1 << 21, 1 << 22, 1 << 23, 1 << 24],
         "gang_queue": [0, 4, 16],

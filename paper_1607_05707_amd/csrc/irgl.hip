@@ -176,9 +176,14 @@ void resolve_tiers(int block, int t_wave, int t_block, int t_grid, int *ow, int 
     *og = g;
 }
 
+// Default workgroup size per kind, from sweeps over road and RMAT graphs:
+// BFS invocations are short, and 1024-thread workgroups cut the barrier
+// arrivals per invocation fourfold; SSSP's longer invocations do best at 512.
+int default_block(int kind) { return kind == IRGL_KIND_BFS ? 1024 : 512; }
+
 irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
-    r.block = (c && c->block) ? c->block : 256;
+    r.block = (c && c->block) ? c->block : default_block(kind);
     if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
     resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, c ? c->t_grid : 0, &r.t_wave, &r.t_block,
                   &r.t_grid);
