@@ -131,7 +131,8 @@ typedef struct irgl_config {
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default: t_grid) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
-                             barrier (default max(2 x block, t_block); lowered to
+                             barrier (default max(2 x block, t_block), in
+                             IRGL_MODE_TOPOLOGY max(512, t_block); lowered to
                              block for a worklist with fewer items than the grid has
                              threads); IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */
@@ -163,10 +164,13 @@ typedef struct irgl_config {
     uint32_t delta;       /* SSSP: near/far threshold step.  Distances below the
                              threshold are expanded in bulk-synchronous invocations;
                              larger ones wait on a far list until the threshold has
-                             risen past them.  0 = the default: when the graph was
-                             uploaded with IRGL_VALIDATE and its mean degree is below
-                             8, 32 x mean weight / mean degree; otherwise
-                             IRGL_DELTA_NONE (plain Bellman-Ford order) */
+                             risen past them.  0 = the default, from the shape of
+                             a graph uploaded with IRGL_VALIDATE (mean weight W,
+                             mean out-degree D, largest out-degree X): D < 8:
+                             32 W / D; D >= 8 and X <= 16 D: 16 W / D; D >= 8,
+                             X > 16 D and at least 2^26 edges: W; otherwise (and
+                             without IRGL_VALIDATE) IRGL_DELTA_NONE (plain
+                             Bellman-Ford order) */
     uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
                              Twelve words per invocation i at 12i: wall-clock tick at
                              its start, incoming worklist size, edges scanned, vertices

@@ -178,19 +178,34 @@ int64_t oracle_edges_scanned(int32_t n, const int32_t *row_ptr, const uint32_t *
  * edge are set to 1, the rest to 0.  component: caller-owned int32[n] or
  * NULL; the smallest vertex id of the vertex's tree.  *edges = forest edges.
  * Returns the forest weight, -1 on invalid arguments / allocation failure,
- * -3 when an edge has no reverse entry of equal weight.
+ * -3 when the CSR is not symmetric: the u > v entries, each named by its
+ * (v, u), must be exactly the u < v entries with equal weights (as multisets).
+ * Sorting both halves by (u, v, w) pairs every edge with its reverse entry.
  */
 typedef struct {
     uint32_t w;
     int32_t u, v;
     int64_t e; /* index of the u -> v entry */
+    int64_t f; /* index of the matching v -> u entry */
 } mst_edge;
 
+/* the total order (w, u, v) */
 static int mst_edge_cmp(const void *a, const void *b) {
     const mst_edge *x = (const mst_edge *)a, *y = (const mst_edge *)b;
     if (x->w != y->w) return x->w < y->w ? -1 : 1;
     if (x->u != y->u) return x->u < y->u ? -1 : 1;
     if (x->v != y->v) return x->v < y->v ? -1 : 1;
+    return 0;
+}
+
+/* pairing order of the two halves of a symmetric CSR: (u, v, w, entry); the
+   rows' own order makes the u < v half almost sorted already */
+static int mst_pair_cmp(const void *a, const void *b) {
+    const mst_edge *x = (const mst_edge *)a, *y = (const mst_edge *)b;
+    if (x->u != y->u) return x->u < y->u ? -1 : 1;
+    if (x->v != y->v) return x->v < y->v ? -1 : 1;
+    if (x->w != y->w) return x->w < y->w ? -1 : 1;
+    if (x->e != y->e) return x->e < y->e ? -1 : 1;
     return 0;
 }
 
@@ -202,54 +217,69 @@ static int32_t uf_find(int32_t *parent, int32_t x) {
     return x;
 }
 
-/* the entry v -> u of v's row with weight wt, or -1 */
-static int64_t reverse_entry(const int32_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t v,
-                             int32_t u, uint32_t wt) {
-    for (int64_t f = row_ptr[v]; f < row_ptr[v + 1]; ++f)
-        if (col[f] == u && w[f] == wt) return f;
-    return -1;
-}
-
 int64_t oracle_kruskal(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
                        uint8_t *in_forest, int32_t *component, int64_t *edges) {
     if (n <= 0 || !row_ptr || !col || !w || !in_forest || !edges) return -1;
     const int64_t m = row_ptr[n];
-    int64_t cnt = 0;
+    int64_t cnt = 0, rcnt = 0;
     for (int32_t u = 0; u < n; ++u)
-        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
             if (u < col[e]) ++cnt;
+            if (u > col[e]) ++rcnt;
+        }
+    if (cnt != rcnt) return -3;
     mst_edge *list = (mst_edge *)malloc((size_t)(cnt > 0 ? cnt : 1) * sizeof(mst_edge));
+    mst_edge *back = (mst_edge *)malloc((size_t)(cnt > 0 ? cnt : 1) * sizeof(mst_edge));
     int32_t *parent = (int32_t *)malloc((size_t)n * sizeof(int32_t));
     int32_t *size = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-    if (!list || !parent || !size) {
+    if (!list || !back || !parent || !size) {
         free(list);
+        free(back);
         free(parent);
         free(size);
         return -1;
     }
-    int64_t k = 0;
+    /* list: the u < v entries; back: the u > v entries, named by (v, u) */
+    int64_t k = 0, r = 0;
     for (int32_t u = 0; u < n; ++u)
-        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
             if (u < col[e]) {
                 list[k].w = w[e];
                 list[k].u = u;
                 list[k].v = col[e];
                 list[k].e = e;
                 ++k;
+            } else if (u > col[e]) {
+                back[r].w = w[e];
+                back[r].u = col[e];
+                back[r].v = u;
+                back[r].e = e;
+                ++r;
             }
+        }
+    /* symmetric input: sorted the same way, the two halves agree entry by
+       entry, and each edge learns its reverse entry */
+    qsort(list, (size_t)cnt, sizeof(mst_edge), mst_pair_cmp);
+    qsort(back, (size_t)cnt, sizeof(mst_edge), mst_pair_cmp);
+    for (int64_t i = 0; i < cnt; ++i) {
+        if (list[i].u != back[i].u || list[i].v != back[i].v || list[i].w != back[i].w) {
+            free(list);
+            free(back);
+            free(parent);
+            free(size);
+            return -3;
+        }
+        list[i].f = back[i].e;
+    }
+    free(back);
     qsort(list, (size_t)cnt, sizeof(mst_edge), mst_edge_cmp);
     for (int32_t v = 0; v < n; ++v) {
         parent[v] = v;
         size[v] = 1;
     }
     memset(in_forest, 0, (size_t)m);
-    int64_t total = 0, taken = 0, status = 0;
+    int64_t total = 0, taken = 0;
     for (int64_t i = 0; i < cnt; ++i) {
-        const int64_t f = reverse_entry(row_ptr, col, w, list[i].v, list[i].u, list[i].w);
-        if (f < 0) {
-            status = -3;
-            break;
-        }
         int32_t a = uf_find(parent, list[i].u), b = uf_find(parent, list[i].v);
         if (a == b) continue;
         if (size[a] < size[b]) {
@@ -260,11 +290,11 @@ int64_t oracle_kruskal(int32_t n, const int32_t *row_ptr, const int32_t *col, co
         parent[b] = a;
         size[a] += size[b];
         in_forest[list[i].e] = 1;
-        in_forest[f] = 1;
+        in_forest[list[i].f] = 1;
         total += list[i].w;
         ++taken;
     }
-    if (status == 0 && component) {
+    if (component) {
         /* the smallest vertex id of each tree, through its root */
         for (int32_t v = 0; v < n; ++v) size[v] = n;
         for (int32_t v = 0; v < n; ++v) {
@@ -277,5 +307,5 @@ int64_t oracle_kruskal(int32_t n, const int32_t *row_ptr, const int32_t *col, co
     free(parent);
     free(size);
     *edges = taken;
-    return status < 0 ? status : total;
+    return total;
 }

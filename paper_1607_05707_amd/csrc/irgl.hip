@@ -67,6 +67,7 @@ struct irgl_graph_s {
     uint32_t flags;
     int device;
     uint64_t weight_sum;  // from IRGL_VALIDATE, else 0
+    uint32_t max_degree;  // largest out-degree, from IRGL_VALIDATE, else 0
     // caller's arrays (batched and served tasks traverse these)
     const int32_t *orig_row_ptr;
     const int32_t *orig_col;
@@ -103,13 +104,22 @@ uint32_t default_t_bitmap(int64_t n, int64_t m) {
     const double t = static_cast<double>(n) * static_cast<double>(n) / (2.0 * static_cast<double>(m));
     return static_cast<uint32_t>(std::max(1.0, std::min(static_cast<double>(n), t)));
 }
-// Default SSSP near/far step.  On low-degree (high-diameter) graphs plain
-// Bellman-Ford rescans long chains many times, so the step is kDeltaScale x
-// mean weight / mean degree; at mean degree kDeltaMinDegree and above
-// (scale-free, low diameter) the extra invocations cost more than the
-// re-relaxations they save, and the default is plain Bellman-Ford.
+// Default SSSP near/far step, from the graph's shape (weights >= 1):
+// * mean degree below kDeltaMinDegree (road-like, high diameter): plain
+//   Bellman-Ford rescans long chains many times; the step is kDeltaScale x
+//   mean weight / mean degree;
+// * denser and near-regular (largest out-degree at most kSkew x the mean):
+//   plain order still re-relaxes every edge 4-6 times; the step is
+//   kDeltaDenseScale x mean weight / mean degree;
+// * denser and scale-free (hubs): plain order re-relaxes ~3 times per edge,
+//   and each near/far step adds a grid barrier per extra invocation; the
+//   saved relaxations repay the barriers only on large graphs (at least
+//   kDeltaSkewMinEdges edges), where the step is the mean weight.
 constexpr double kDeltaScale = 32.0;
+constexpr double kDeltaDenseScale = 16.0;
 constexpr double kDeltaMinDegree = 8.0;
+constexpr double kSkew = 16.0;
+constexpr int64_t kDeltaSkewMinEdges = int64_t(1) << 26;
 
 uint32_t default_delta(const irgl_graph_s *g);
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -181,19 +191,28 @@ void resolve_tiers(int block, int t_wave, int t_block, int t_grid, int *ow, int 
 // arrivals per invocation fourfold; SSSP's longer invocations do best at 512.
 int default_block(int kind) { return kind == IRGL_KIND_BFS ? 1024 : 512; }
 
+// Grid-tier threshold of topology-driven invocations (RMAT-22 SSSP: 12.7 ms
+// per query at 512 against 20.2 ms at 1024 with 512-thread workgroups; with
+// 1024-thread workgroups 13.0 ms at 512, 17.2 ms at 256, 20.4 ms at 2048).
+constexpr int kTopoGridTier = 512;
+
 irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
     r.block = (c && c->block) ? c->block : default_block(kind);
     if (r.block != 256 && r.block != 512 && r.block != 1024) return IRGL_ERR_CONFIG;
-    resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, c ? c->t_grid : 0, &r.t_wave, &r.t_block,
-                  &r.t_grid);
+    r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
+    if (r.mode != IRGL_MODE_PERSISTENT && r.mode != IRGL_MODE_HOST_LOOP && r.mode != IRGL_MODE_TOPOLOGY)
+        return IRGL_ERR_CONFIG;
+    // A topology-driven invocation visits every vertex, so every hub of the
+    // graph passes the tiers each time: the grid tier takes them from a fixed
+    // kTopoGridTier edges on, whatever the workgroup size
+    int t_grid = c ? c->t_grid : 0;
+    if (t_grid == 0 && r.mode == IRGL_MODE_TOPOLOGY) t_grid = std::max(kTopoGridTier, c ? c->t_block : 0);
+    resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, t_grid, &r.t_wave, &r.t_block, &r.t_grid);
     if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
         return IRGL_ERR_CONFIG;
     r.grid = c ? c->grid : 0;
     if (r.grid < 0) return IRGL_ERR_CONFIG;
-    r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
-    if (r.mode != IRGL_MODE_PERSISTENT && r.mode != IRGL_MODE_HOST_LOOP && r.mode != IRGL_MODE_TOPOLOGY)
-        return IRGL_ERR_CONFIG;
     r.reduce = c ? c->reduce : IRGL_REDUCE_ANY;
     if (r.reduce != IRGL_REDUCE_ANY && r.reduce != IRGL_REDUCE_ALL) return IRGL_ERR_CONFIG;
     const uint32_t n = static_cast<uint32_t>(g->n);
@@ -746,17 +765,26 @@ uint32_t default_delta(const irgl_graph_s *g) {
     if (!g->weight_sum || g->m <= 0 || g->n <= 0) return IRGL_DELTA_NONE;
     const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
     const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
-    if (mean_deg >= kDeltaMinDegree) return IRGL_DELTA_NONE;
-    const double d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
+    double d;
+    if (mean_deg < kDeltaMinDegree) {
+        d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
+    } else if (static_cast<double>(g->max_degree) <= kSkew * mean_deg) {
+        d = kDeltaDenseScale * mean_w / mean_deg;
+    } else {
+        if (g->m < kDeltaSkewMinEdges) return IRGL_DELTA_NONE;
+        d = mean_w;
+    }
     return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
 }
 
 __device__ uint32_t g_invalid_flag;
 __device__ unsigned long long g_weight_sum;
+__device__ uint32_t g_max_degree;
 
 __global__ void clear_flag_kernel() {
     g_invalid_flag = 0u;
     g_weight_sum = 0ull;
+    g_max_degree = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -890,9 +918,10 @@ irgl_status irgl_wallclock_khz(int32_t *khz) {
     return IRGL_OK;
 }
 
-// Argument checks, the device, and (IRGL_VALIDATE) the on-device CSR check
-// and weight sum; shared by both uploads.
-static irgl_status upload_prologue(const irgl_csr *csr, int *dev_out, unsigned long long *wsum_out) {
+// Argument checks, the device, and (IRGL_VALIDATE) the on-device CSR check,
+// weight sum and largest out-degree; shared by both uploads.
+static irgl_status upload_prologue(const irgl_csr *csr, int *dev_out, unsigned long long *wsum_out,
+                                   uint32_t *maxdeg_out) {
     if (csr->n <= 0 || csr->m < 0 || csr->m >= (int64_t(1) << 31)) return IRGL_ERR_INVALID_ARGUMENT;
     if (!csr->row_ptr || (csr->m > 0 && !csr->col)) return IRGL_ERR_INVALID_ARGUMENT;
     int count = 0;
@@ -904,23 +933,28 @@ static irgl_status upload_prologue(const irgl_csr *csr, int *dev_out, unsigned l
     IRGL_HIP(hipGetDevice(&dev));
     *dev_out = dev;
     unsigned long long weight_sum = 0;
+    uint32_t max_degree = 0;
     if (csr->flags & IRGL_VALIDATE) {
         hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, 0);
         IRGL_HIP(hipGetLastError());
         uint32_t *flag = nullptr;
         unsigned long long *wsum = nullptr;
+        uint32_t *maxdeg = nullptr;
         IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&flag), HIP_SYMBOL(g_invalid_flag)));
         IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&wsum), HIP_SYMBOL(g_weight_sum)));
-        const int grid = std::min<int64_t>(4096, std::max<int64_t>(1, (csr->m + 255) / 256));
+        IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&maxdeg), HIP_SYMBOL(g_max_degree)));
+        const int grid = std::min<int64_t>(4096, std::max<int64_t>(1, (std::max<int64_t>(csr->m, csr->n) + 255) / 256));
         hipLaunchKernelGGL(validate_kernel, dim3(grid), dim3(256), 0, 0, csr->n, csr->m, csr->row_ptr,
-                           csr->col, csr->w, flag, wsum);
+                           csr->col, csr->w, flag, wsum, maxdeg);
         IRGL_HIP(hipGetLastError());
         uint32_t bad = 0;
         IRGL_HIP(hipMemcpy(&bad, flag, 4, hipMemcpyDeviceToHost));
         if (bad) return IRGL_ERR_INVALID_GRAPH;
         IRGL_HIP(hipMemcpy(&weight_sum, wsum, 8, hipMemcpyDeviceToHost));
+        IRGL_HIP(hipMemcpy(&max_degree, maxdeg, 4, hipMemcpyDeviceToHost));
     }
     *wsum_out = csr->w ? weight_sum : 0ull;
+    *maxdeg_out = max_degree;
     return IRGL_OK;
 }
 
@@ -929,7 +963,8 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     *out = nullptr;
     int dev = 0;
     unsigned long long weight_sum = 0;
-    irgl_status st = upload_prologue(csr, &dev, &weight_sum);
+    uint32_t max_degree = 0;
+    irgl_status st = upload_prologue(csr, &dev, &weight_sum, &max_degree);
     if (st) return st;
     irgl_graph_s *g = new (std::nothrow) irgl_graph_s;
     if (!g) return IRGL_ERR_INVALID_ARGUMENT;
@@ -941,6 +976,7 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     g->flags = csr->flags;
     g->device = dev;
     g->weight_sum = csr->w ? weight_sum : 0;
+    g->max_degree = max_degree;
     g->orig_row_ptr = csr->row_ptr;
     g->orig_col = csr->col;
     g->orig_w = csr->w;
@@ -963,7 +999,8 @@ irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t
     *out = nullptr;
     int dev = 0;
     unsigned long long weight_sum = 0;
-    irgl_status st = upload_prologue(csr, &dev, &weight_sum);
+    uint32_t max_degree = 0;
+    irgl_status st = upload_prologue(csr, &dev, &weight_sum, &max_degree);
     if (st) return st;
     const int32_t n = csr->n;
     const int64_t m = csr->m;
@@ -1010,6 +1047,7 @@ irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t
     g->flags = csr->flags;
     g->device = dev;
     g->weight_sum = weight_sum;
+    g->max_degree = max_degree;
     g->orig_row_ptr = csr->row_ptr;
     g->orig_col = csr->col;
     g->orig_w = csr->w;

@@ -643,14 +643,24 @@ __global__ void scatter_results_kernel(int32_t n, const int32_t *perm, const uin
 }
 
 // On-device CSR validation: row_ptr[0] == 0, monotone, row_ptr[n] == m,
-// col in [0, n), w >= 1.  Sets *bad to 1 on any violation.
+// col in [0, n), w >= 1.  Sets *bad to 1 on any violation; also sums the
+// weights and takes the largest out-degree (one atomic per wavefront).
 __global__ void validate_kernel(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
-                                const uint32_t *w, uint32_t *bad, unsigned long long *wsum) {
+                                const uint32_t *w, uint32_t *bad, unsigned long long *wsum, uint32_t *maxdeg) {
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
     if (tid == 0 && (row_ptr[0] != 0 || static_cast<int64_t>(row_ptr[n]) != m)) atomicOr(bad, 1u);
-    for (uint32_t v = tid; v < static_cast<uint32_t>(n); v += stride)
-        if (row_ptr[v + 1] < row_ptr[v]) atomicOr(bad, 1u);
+    int32_t dmax = 0;
+    for (uint32_t v = tid; v < static_cast<uint32_t>(n); v += stride) {
+        const int32_t d = row_ptr[v + 1] - row_ptr[v];
+        if (d < 0) atomicOr(bad, 1u);
+        dmax = d > dmax ? d : dmax;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const int32_t x = __shfl_xor(dmax, o);
+        dmax = x > dmax ? x : dmax;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && dmax > 0) atomicMax(maxdeg, static_cast<uint32_t>(dmax));
     unsigned long long ws = 0;
     for (uint64_t e = tid; e < static_cast<uint64_t>(m); e += stride) {
         const int32_t d = col[e];

@@ -191,3 +191,26 @@ def test_asymmetric_input_is_rejected():
     g = gg.from_edges(3, [0, 1], [1, 2], [4, 5], name="directed")
     with pytest.raises(ValueError):
         oracle.kruskal(*g.numpy())
+
+
+def test_asymmetric_weights_and_one_sided_reverse_are_rejected():
+    # 0-1 stored both ways but with different weights
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    c = np.array([1, 0], dtype=np.int32)
+    with pytest.raises(ValueError):
+        oracle.kruskal(rp, c, np.array([3, 4], dtype=np.uint32))
+    # only the u > v entry of an edge (the other half is empty)
+    rp = np.array([0, 0, 1], dtype=np.int32)
+    with pytest.raises(ValueError):
+        oracle.kruskal(rp, np.array([0], dtype=np.int32), np.array([3], dtype=np.uint32))
+
+
+def test_parallel_edges_take_the_lighter_copy():
+    # 0-1 twice (weights 7 and 2, each stored both ways), 1-2 once (weight 5)
+    rp = np.array([0, 2, 5, 6], dtype=np.int32)
+    c = np.array([1, 1, 0, 0, 2, 1], dtype=np.int32)
+    w = np.array([7, 2, 2, 7, 5, 5], dtype=np.uint32)
+    weight, in_forest, comp, ne = oracle.kruskal(rp, c, w)
+    assert (weight, ne) == (7, 2)
+    assert in_forest.tolist() == [0, 1, 1, 0, 1, 1]
+    assert comp.tolist() == [0, 0, 0]
