@@ -248,6 +248,13 @@ irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t
 /* Release a handle (not the arrays it borrows).  NULL is accepted. */
 irgl_status irgl_graph_free(irgl_graph g);
 
+/* The SSSP near/far step that a query on g uses when its configuration leaves
+ * delta at 0 (the rule is given at irgl_config.delta; the mean weight, mean
+ * and largest out-degree come from the upload's IRGL_VALIDATE pass).  *delta
+ * receives IRGL_DELTA_NONE for plain Bellman-Ford order.  No device work.
+ * Errors: INVALID_ARGUMENT (null g or delta). */
+irgl_status irgl_graph_default_delta(irgl_graph g, uint32_t *delta);
+
 /* Bytes of device workspace one query of `kind` needs on graph g with the
  * given config (NULL = defaults).  The workspace holds the two worklists of
  * the pipe context (Section 4.2: "in" and "out"), the loop's counters and

@@ -1061,6 +1061,12 @@ irgl_status irgl_graph_free(irgl_graph g) {
     return IRGL_OK;
 }
 
+irgl_status irgl_graph_default_delta(irgl_graph g, uint32_t *delta) {
+    if (!g || !delta) return IRGL_ERR_INVALID_ARGUMENT;
+    *delta = default_delta(g);
+    return IRGL_OK;
+}
+
 irgl_status irgl_workspace_bytes(irgl_graph g, int32_t kind, int32_t with_parent,
                                  const irgl_config *cfg, size_t *bytes) {
     if (!g || !bytes) return IRGL_ERR_INVALID_ARGUMENT;

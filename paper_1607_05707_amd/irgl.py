@@ -102,6 +102,8 @@ _lib.irgl_graph_upload_reordered.restype = ctypes.c_int32
 _lib.irgl_graph_upload_reordered.argtypes = [ctypes.POINTER(irgl_csr), _c, ctypes.c_size_t, ctypes.POINTER(_c)]
 _lib.irgl_graph_free.restype = ctypes.c_int32
 _lib.irgl_graph_free.argtypes = [_c]
+_lib.irgl_graph_default_delta.restype = ctypes.c_int32
+_lib.irgl_graph_default_delta.argtypes = [_c, ctypes.POINTER(ctypes.c_uint32)]
 _lib.irgl_workspace_bytes.restype = ctypes.c_int32
 _lib.irgl_workspace_bytes.argtypes = [_c, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(irgl_config),
                                       ctypes.POINTER(ctypes.c_size_t)]
@@ -430,6 +432,13 @@ def query(g: Graph, kind: int, src: int, with_parent: bool = False, cfg=None, st
     if check and st["status"] != IRGL_OK:
         raise IrglError(st["status"], "device")
     return out, parent, st
+
+
+def irgl_graph_default_delta(g: Graph) -> int:
+    """The SSSP near/far step a query on g takes when its delta is left at 0."""
+    out = ctypes.c_uint32()
+    _check(_lib.irgl_graph_default_delta(g.handle, ctypes.byref(out)), "irgl_graph_default_delta")
+    return int(out.value)
 
 
 def upload(g, flags: int = IRGL_VALIDATE, reorder: bool = False) -> Graph:

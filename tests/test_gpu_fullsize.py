@@ -93,6 +93,9 @@ def test_rmat22_sssp_full_size(irgl, rmat22):
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     ws = irgl.workspace(hg, SSSP, False, BENCH_CFG)
     stats = irgl.stats_tensor(dev)
+    # scale-free with more than 2^26 edges: the near/far step is the mean weight
+    mean_w = float(np.asarray(w, dtype=np.uint32).astype(np.uint64).sum()) / g.m
+    assert irgl.irgl_graph_default_delta(hg) == int(mean_w)
     for i in (0, 31, 63):
         src = g.sources[i]
         _say(f"rmat22 SSSP source #{i} ({src}), bench configuration, against the oracle")

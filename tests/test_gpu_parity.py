@@ -367,3 +367,48 @@ def test_watchdog_and_abort_forced_from_host(irgl):
     # a cleared flag does not disturb the query
     flag.zero_()
     _check_query(irgl, g, hg, BFS, 0, {"abort_flag": flag.data_ptr()})
+
+
+def _expected_default_delta(g, validated=True):
+    """The default near/far step written out from the graph's shape: mean
+    weight W, mean out-degree D, largest out-degree X (host arrays)."""
+    rp, col, w = g.numpy()
+    if not validated or w is None or g.m == 0:
+        return 0xFFFFFFFF
+    mean_w = float(np.asarray(w, dtype=np.uint32).astype(np.uint64).sum()) / g.m
+    mean_deg = g.m / g.n
+    x = int(np.diff(rp).max())
+    if mean_deg < 8.0:
+        d = 32.0 * mean_w / max(1.0, mean_deg)
+    elif x <= 16.0 * mean_deg:
+        d = 16.0 * mean_w / mean_deg
+    elif g.m >= 1 << 26:
+        d = mean_w
+    else:
+        return 0xFFFFFFFF
+    return int(min(4.0e9, max(1.0, d)))
+
+
+def test_default_near_far_step(irgl):
+    cases = [
+        (gg.uniform_random(1 << 14, 16.0, seed=61, weight_seed=62, wmax=1000), "near-regular, D 16"),
+        (gg.uniform_random(1 << 14, 32.0, seed=63, weight_seed=64, wmax=1000), "near-regular, D 32"),
+        (gg.rmat(14, seed=65, weight_seed=66, wmax=255), "scale-free, below 2^26 edges"),
+        (gg.config_road(width=64), "road-like, D < 8"),
+        (gg.rmat(12, seed=67), "unweighted"),
+    ]
+    seen = set()
+    for g, what in cases:
+        g = _dev(g)
+        want = _expected_default_delta(g)
+        _say(f"default near/far step: {what} ({g.name}) -> {want}")
+        for reorder in (False, True):
+            assert irgl.irgl_graph_default_delta(irgl.upload(g, reorder=reorder)) == want, (what, reorder)
+        seen.add(want == 0xFFFFFFFF)
+        if g.w is not None:
+            src = g.sources[0] if g.sources else 0
+            _check_query(irgl, g, irgl.upload(g), SSSP, src, with_parent=False)
+    assert seen == {True, False}
+    # without the validation pass the shape is unknown: plain Bellman-Ford order
+    g = _dev(gg.uniform_random(1 << 12, 16.0, seed=68, weight_seed=69, wmax=1000))
+    assert irgl.irgl_graph_default_delta(irgl.upload(g, flags=0)) == 0xFFFFFFFF
