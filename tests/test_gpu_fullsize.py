@@ -8,7 +8,8 @@ configurations the benchmark times, against the CPU oracle.
   by element (BFS levels on 16 of the 64 sources, SSSP distances on 3);
   two more SSSP sources are pinned by the distance certificate
   (``oracle.validate``), which holds for exactly one distance vector; one
-  BFS with parents checks the parent tree.  The minimum spanning forest of
+  BFS with parents checks the parent tree.  One source in the topology-driven
+  and host-loop launch forms, against the oracle.  The minimum spanning forest of
   the same graph (packed atomic section) is compared with Kruskal's: weight,
   every CSR entry's mark and every vertex's component.
 * the batched workload (320 tasks: 256 uniform graphs of uneven size plus
@@ -108,6 +109,31 @@ def test_rmat22_sssp_full_size(irgl, rmat22):
         _say(f"rmat22 SSSP source #{i} ({src}), distance certificate")
         got, _ = _run(irgl, hg, irgl.irgl_sssp, SSSP, src, out, ws, stats)
         oracle.validate(rp, col, src, got, None, w)
+
+
+def test_rmat22_topology_driven_and_host_loop_full_size(irgl, rmat22):
+    # the other two launch forms on the same graph and source: topology-driven
+    # Iterate (every invocation a ForAll over all vertices, ReduceAndReturn Any)
+    # and one launch per invocation from the host
+    g, hg, rp, col, w = rmat22
+    dev = hg.row_ptr.device
+    src = g.sources[5]
+    refs = {BFS: oracle.bfs(rp, col, src, with_parent=False)[0],
+            SSSP: oracle.dijkstra(rp, col, w, src, with_parent=False)[0]}
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    stats = irgl.stats_tensor(dev)
+    for mode in (irgl.IRGL_MODE_TOPOLOGY, irgl.IRGL_MODE_HOST_LOOP):
+        for kind, fn in ((BFS, irgl.irgl_bfs), (SSSP, irgl.irgl_sssp)):
+            cfg = {"mode": mode}
+            _say(f"rmat22 kind={kind} source #5 ({src}) mode={mode}")
+            ws = irgl.workspace(hg, kind, False, cfg)
+            fn(hg, src, out, None, ws, None, stats, cfg)
+            st = irgl.read_stats(stats)
+            assert st["status"] == 0, irgl.irgl_status_string(st["status"])
+            np.testing.assert_array_equal(irgl.as_u32_numpy(out), refs[kind],
+                                          err_msg=f"rmat22 kind={kind} mode={mode}")
+            if mode == irgl.IRGL_MODE_TOPOLOGY:
+                assert st["items"] == g.n * st["iterations"]
 
 
 def test_rmat22_spanning_forest_full_size(irgl, rmat22):
