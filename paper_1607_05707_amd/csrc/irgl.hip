@@ -191,10 +191,12 @@ void resolve_tiers(int block, int t_wave, int t_block, int t_grid, int *ow, int 
 // arrivals per invocation fourfold; SSSP's longer invocations do best at 512.
 int default_block(int kind) { return kind == IRGL_KIND_BFS ? 1024 : 512; }
 
-// Grid-tier threshold of topology-driven invocations (RMAT-22 SSSP: 12.7 ms
-// per query at 512 against 20.2 ms at 1024 with 512-thread workgroups; with
-// 1024-thread workgroups 13.0 ms at 512, 17.2 ms at 256, 20.4 ms at 2048).
-constexpr int kTopoGridTier = 512;
+// Default grid-tier threshold of single queries, whatever the workgroup size
+// (RMAT-22 SSSP at 512-thread workgroups: 4.73 ms per query at 512 against
+// 4.84 ms at 1024; topology-driven 12.7 ms against 20.2 ms, and with
+// 1024-thread workgroups 13.0 ms at 512, 17.2 ms at 256, 20.4 ms at 2048;
+// BFS within 2% from 512 to 4096).
+constexpr int kGridTier = 512;
 
 irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
@@ -203,11 +205,9 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
     r.mode = c ? c->mode : IRGL_MODE_PERSISTENT;
     if (r.mode != IRGL_MODE_PERSISTENT && r.mode != IRGL_MODE_HOST_LOOP && r.mode != IRGL_MODE_TOPOLOGY)
         return IRGL_ERR_CONFIG;
-    // A topology-driven invocation visits every vertex, so every hub of the
-    // graph passes the tiers each time: the grid tier takes them from a fixed
-    // kTopoGridTier edges on, whatever the workgroup size
+    // the grid tier takes hubs from a fixed kGridTier edges on
     int t_grid = c ? c->t_grid : 0;
-    if (t_grid == 0 && r.mode == IRGL_MODE_TOPOLOGY) t_grid = std::max(kTopoGridTier, c ? c->t_block : 0);
+    if (t_grid == 0) t_grid = std::max(kGridTier, c ? c->t_block : 0);
     resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, t_grid, &r.t_wave, &r.t_block, &r.t_grid);
     if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
         return IRGL_ERR_CONFIG;
