@@ -4,14 +4,17 @@ configurations the benchmark times, against the CPU oracle.
 * RMAT-22 (scale 22, edge factor 16, symmetrized: n = 4,194,304,
   m = 128,313,176), degree-sorted relabelling at upload, the library's
   default configuration, one launch per query into one reused workspace,
-  no parent output.  Sampled sources are compared with the oracle element
-  by element (BFS levels on 16 of the 64 sources, SSSP distances on 3);
+  no parent output.  Sources are compared with the oracle element by
+  element (BFS levels and level histograms on all 64, SSSP distances on 3);
   two more SSSP sources are pinned by the distance certificate
   (``oracle.validate``), which holds for exactly one distance vector; one
   BFS with parents checks the parent tree.  One source in the topology-driven
   and host-loop launch forms, against the oracle.  The minimum spanning forest of
   the same graph (packed atomic section) is compared with Kruskal's: weight,
   every CSR entry's mark and every vertex's component.
+* the road-like 4096 x 4096 grid (16.7M vertices, weights up to 10000),
+  with and without its long edges (the latter ~8,190 BFS levels in one
+  launch): BFS and SSSP from source 0 against the oracle.
 * the batched workload (320 tasks: 256 uniform graphs of uneven size plus
   R-MAT-20 with 64 BFS sources) in one launch with the stored batch
   configuration; every fourth task is compared with the oracle.
@@ -68,7 +71,7 @@ def test_rmat22_bfs_full_size(irgl, rmat22):
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     ws = irgl.workspace(hg, BFS, False, BENCH_CFG)
     stats = irgl.stats_tensor(dev)
-    for i in range(0, 64, 4):
+    for i in range(64):
         src = g.sources[i]
         _say(f"rmat22 BFS source #{i} ({src}), bench configuration")
         got, st = _run(irgl, hg, irgl.irgl_bfs, BFS, src, out, ws, stats)
@@ -79,6 +82,7 @@ def test_rmat22_bfs_full_size(irgl, rmat22):
         assert st["frontier_edges"] == oracle.edges_scanned(rp, ref)
         assert st["iterations"] == int(ref[reached].max()) + 1
         assert st["block"] == 1024
+        np.testing.assert_array_equal(oracle.level_histogram(got), oracle.level_histogram(ref))
     # parents: any valid BFS tree; the validator checks it against the levels
     src = g.sources[1]
     _say(f"rmat22 BFS source #1 ({src}) with parents")
@@ -148,6 +152,31 @@ def test_rmat22_spanning_forest_full_size(irgl, rmat22):
     assert st["frontier_edges"] == ref_ne
     np.testing.assert_array_equal(comp.cpu().numpy(), ref_c)
     np.testing.assert_array_equal(in_forest.cpu().numpy(), ref_f)
+
+
+@pytest.mark.parametrize("long_edges", [True, False])
+def test_road4096_full_size(irgl, long_edges):
+    # the road-like 4096 x 4096 grid (16.7M vertices), relabelled upload and
+    # default configuration; without the long edges BFS runs ~8,190 levels,
+    # one grid barrier each, in one launch
+    dev = torch.device("cuda:0")
+    g = gg.config_road(device=dev, long_edges=long_edges)
+    hg = irgl.upload(g, reorder=True)
+    rp, col, w = g.numpy()
+    src = g.sources[0]
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    stats = irgl.stats_tensor(dev)
+    for kind, fn in ((BFS, irgl.irgl_bfs), (SSSP, irgl.irgl_sssp)):
+        _say(f"{g.name} kind={kind} source {src}, default configuration")
+        ws = irgl.workspace(hg, kind, False, BENCH_CFG)
+        got, st = _run(irgl, hg, fn, kind, src, out, ws, stats)
+        ref = oracle.bfs(rp, col, src, with_parent=False)[0] if kind == BFS else \
+            oracle.dijkstra(rp, col, w, src, with_parent=False)[0]
+        np.testing.assert_array_equal(got, ref, err_msg=f"{g.name} kind={kind}")
+        if kind == BFS:
+            assert st["iterations"] == int(ref[ref != oracle.INF].max()) + 1
+            if not long_edges:
+                assert st["iterations"] > 8000
 
 
 def test_batched_workload_full_size(irgl):
