@@ -408,7 +408,7 @@ def main() -> int:
         "traffic": traffic,
         "traffic_unit": "bytes per launch",
         "alg_bytes_per_launch": ks["alg_bytes_per_query"],
-        "kernel": f"{kname} (+ its init fill)",
+        "kernel": f"{kname} (timed with its init fill and the scatter of results to caller ids)",
     }
 
     mst = None
