@@ -217,7 +217,9 @@ irgl_status irgl_wallclock_khz(int32_t *khz);
 /* Register a device-resident CSR graph (Section 4.1: the graph whose
  * edges(n) the BFS kernel iterates).  *out receives a handle that borrows the
  * caller's arrays.  With IRGL_VALIDATE the CSR is checked on the device and
- * the call synchronizes; a malformed graph gives IRGL_ERR_INVALID_GRAPH.
+ * the call synchronizes; a malformed graph gives IRGL_ERR_INVALID_GRAPH.  The
+ * same pass sums the weights and finds the largest out-degree, from which the
+ * SSSP near/far step defaults (irgl_config.delta).
  * Errors: INVALID_ARGUMENT (null csr/out/row_ptr, null col with m > 0,
  * n <= 0, m < 0, m >= 2^31), NO_DEVICE, DEVICE. */
 irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out);
