@@ -178,8 +178,12 @@ typedef struct irgl_config {
                              SSSP atomicMin), claim atomics won, largest and summed
                              per-workgroup busy ticks of the expansion phase, the same
                              for the grid-tier phase, 0; then the end tick at
-                             12 x iterations.  All but the first two words are
-                             recorded by top-down invocations in persistent mode */
+                             12 x iterations.  In persistent mode top-down
+                             invocations fill every word, bottom-up invocations
+                             all but the busy ticks, and SSSP far-to-near transfer
+                             invocations only the first two; in host-loop mode
+                             every invocation writes its first two words;
+                             topology-driven launches record no trace */
     uint32_t barrier;     /* grid-barrier coherence scheme: IRGL_BARRIER_XCD (default:
                              one L2 write-back per XCD per barrier) or
                              IRGL_BARRIER_WORKGROUP (write-back and invalidate per

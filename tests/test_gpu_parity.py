@@ -412,3 +412,49 @@ def test_default_near_far_step(irgl):
     # without the validation pass the shape is unknown: plain Bellman-Ford order
     g = _dev(gg.uniform_random(1 << 12, 16.0, seed=68, weight_seed=69, wmax=1000))
     assert irgl.irgl_graph_default_delta(irgl.upload(g, flags=0)) == 0xFFFFFFFF
+
+
+def test_trace_records_the_body_each_invocation_ran(irgl):
+    # One outlined launch picks a loop body per invocation at run time
+    # (dynamic piping).  BFS on a symmetric R-MAT graph: top-down invocations
+    # record their expansion's busy ticks (word 8), bottom-up ones the edges
+    # they scanned but no busy ticks.  SSSP with a near/far step: far-to-near
+    # transfer invocations start from an empty worklist and record nothing
+    # past their first two words.
+    dev = torch.device("cuda:0")
+    k_words = 12
+    for g, kind, what in ((_dev(gg.rmat(16, seed=71, weight_seed=72, wmax=255)), BFS, "rmat16 BFS"),
+                          (_dev(gg.config_road(width=128)), SSSP, "road128 SSSP")):
+        hg = irgl.upload(g)
+        src = gg.pick_sources(g, 1, seed=73)[0]
+        tr = torch.zeros(k_words * 4096 + 1, dtype=torch.int64, device=dev)
+        _say(f"trace: {what} src={src}")
+        out, _, st = irgl.query(hg, kind, src, with_parent=False, cfg={"trace": tr, "trace_len": tr.numel()})
+        rp, col, w = g.numpy()
+        ref = oracle.bfs(rp, col, src)[0] if kind == BFS else oracle.dijkstra(rp, col, w, src)[0]
+        np.testing.assert_array_equal(irgl.as_u32_numpy(out), ref)
+        it = st["iterations"]
+        assert 0 < it < 4096
+        t = tr.cpu().numpy()
+        starts, sizes, scanned = t[0:k_words * it:k_words], t[1:k_words * it:k_words], t[2:k_words * it:k_words]
+        busy = t[8:k_words * it:k_words]
+        assert (np.diff(starts) >= 0).all() and t[k_words * it] >= starts[-1] > 0
+        assert sizes[0] == 1 and int(sizes.sum()) == st["items"]
+        assert int(scanned.sum()) <= st["edges"]
+        assert not t[k_words * it + 1:].any()  # nothing written past the end tick
+        if kind == BFS:
+            assert ((sizes > 0) & (busy == 0) & (scanned > 0)).any(), "no bottom-up invocation"
+            assert (busy > 0).any(), "no top-down invocation"
+        else:
+            assert irgl.irgl_graph_default_delta(hg) != 0xFFFFFFFF
+            transfer = sizes == 0
+            assert transfer.any(), "no transfer invocation"
+            assert not t[:k_words * it].reshape(it, k_words)[transfer][:, 2:].any()
+            assert (busy > 0).any() and (scanned > 0).any()
+    # a trace shorter than the run: words past trace_len stay untouched
+    g = _dev(gg.config_road(width=64))
+    hg = irgl.upload(g)
+    tr = torch.full((64,), -1, dtype=torch.int64, device=dev)
+    _, _, st = irgl.query(hg, BFS, 0, with_parent=False, cfg={"trace": tr, "trace_len": 2 * k_words})
+    assert st["iterations"] > 2
+    assert (tr.cpu().numpy()[2 * k_words:] == -1).all()
