@@ -442,6 +442,8 @@ def test_trace_records_the_body_each_invocation_ran(irgl):
         assert sizes[0] == 1 and int(sizes.sum()) == st["items"]
         assert int(scanned.sum()) <= st["edges"]
         assert not t[k_words * it + 1:].any()  # nothing written past the end tick
+        khz = irgl.irgl_wallclock_khz()  # converts the ticks to time
+        assert khz > 0 and 0 < (t[k_words * it] - starts[0]) / khz < 10_000
         if kind == BFS:
             assert ((sizes > 0) & (busy == 0) & (scanned > 0)).any(), "no bottom-up invocation"
             assert (busy > 0).any(), "no top-down invocation"
@@ -458,3 +460,4 @@ def test_trace_records_the_body_each_invocation_ran(irgl):
     _, _, st = irgl.query(hg, BFS, 0, with_parent=False, cfg={"trace": tr, "trace_len": 2 * k_words})
     assert st["iterations"] > 2
     assert (tr.cpu().numpy()[2 * k_words:] == -1).all()
+    assert isinstance(irgl.irgl_last_hip_error(), int)
