@@ -1,6 +1,7 @@
-"""Host logic of the HBM-traffic measurement (no GPU, no profiler): the
-counter scaling against the calibration copy, and the guard that drops a
-recorded traffic figure once the kernels' sources have changed."""
+"""Host logic of the measurement (no GPU, no profiler): the HBM-traffic
+counter scaling against the calibration copy, the guard that drops a
+recorded traffic figure once the kernels' sources have changed, and the
+benchmark's refusal of more than one GPU."""
 import json
 
 import pytest
@@ -54,3 +55,15 @@ def test_digest_covers_every_kernel_source():
     assert "irgl.hip" in names
     for h in ("irgl_device.h", "irgl_ops.h", "irgl_expand.h", "irgl_query.h", "irgl_batch.h", "irgl_topo.h"):
         assert h in names
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: the refusal comes before anything touches a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
