@@ -217,6 +217,14 @@ int32_t irgl_last_hip_error(void);
 /* Wall-clock tick rate (kHz) of the device the calling thread uses, for
  * converting `trace` entries to time. */
 irgl_status irgl_wallclock_khz(int32_t *khz);
+/* Return the library's process-lifetime host resources (the pinned read-back
+ * words of IRGL_MODE_HOST_LOOP queries) to the HIP runtime.  Call it once no
+ * query is running, before the process exits: the library frees nothing from
+ * static destructors, which may run after the HIP runtime has been torn down.
+ * Graphs, batches and servers are released by their own free/close calls.
+ * The library stays usable afterwards (a later host-loop query allocates a
+ * new word).  Returns IRGL_ERR_DEVICE if a free failed. */
+irgl_status irgl_shutdown(void);
 
 /* Register a device-resident CSR graph (Section 4.1: the graph whose
  * edges(n) the BFS kernel iterates).  *out receives a handle that borrows the

@@ -12,6 +12,10 @@ HIP library and never calls it.
 * ``floyd_warshall``: all-pairs min-plus closure in numpy, for tiny graphs.
 * ``validate``: the invariants that characterize exact distances plus a
   valid parent tree, vectorized over the CSR.
+* ``certify``: the same distance invariants as one serial C pass
+  (``oracle_certify``), fast enough to check every full-size output.
+* ``edges_scanned``: the TEPS numerator, the out-degree sum of the reached
+  vertices (pinned by closed forms).
 """
 from __future__ import annotations
 
@@ -44,6 +48,9 @@ def _load():
         lib.oracle_dijkstra.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, u32p, i32p]
         lib.oracle_edges_scanned.restype = ctypes.c_int64
         lib.oracle_edges_scanned.argtypes = [ctypes.c_int32, i32p, u32p]
+        lib.oracle_certify.restype = ctypes.c_int64
+        lib.oracle_certify.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.c_int32, u32p,
+                                       ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_kruskal.restype = ctypes.c_int64
         lib.oracle_kruskal.argtypes = [ctypes.c_int32, i32p, i32p, u32p, ctypes.POINTER(ctypes.c_uint8), i32p,
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -99,6 +106,35 @@ def edges_scanned(row_ptr, level) -> int:
     lv = np.ascontiguousarray(level, dtype=np.uint32)
     return int(_load().oracle_edges_scanned(rp.size - 1, _ptr(rp, ctypes.c_int32),
                                             _ptr(lv, ctypes.c_uint32)))
+
+
+_CERT_WHAT = {1: "d[src] != 0", 2: "an edge u -> v with d[v] > d[u] + w (or v unreached)",
+              3: "a reached vertex without a tight in-edge", 4: "a zero weight"}
+
+
+def certify(row_ptr, col, src: int, d, w=None) -> None:
+    """Raise ValidationError unless ``d`` is exactly the shortest-path (BFS
+    when ``w`` is None) distance vector from ``src``: the same three
+    conditions as ``validate`` without parents, as one serial C pass
+    (``oracle_certify``) that is fast enough for every full-size output."""
+    rp, c = _csr(row_ptr, col)
+    dd = np.ascontiguousarray(d).view(np.uint32) if np.asarray(d).dtype.itemsize == 4 else \
+        np.ascontiguousarray(d, dtype=np.uint32)
+    n = rp.size - 1
+    if dd.size != n:
+        raise ValidationError(f"distance array has {dd.size} entries, expected {n}")
+    ww = None
+    if w is not None:
+        ww = np.ascontiguousarray(w).view(np.uint32) if np.asarray(w).dtype.itemsize == 4 else \
+            np.ascontiguousarray(w, dtype=np.uint32)
+    where = ctypes.c_int64()
+    r = _load().oracle_certify(n, _ptr(rp, ctypes.c_int32), _ptr(c, ctypes.c_int32),
+                               _ptr(ww, ctypes.c_uint32) if ww is not None else None, int(src),
+                               _ptr(dd, ctypes.c_uint32), ctypes.byref(where))
+    if r < 0:
+        raise ValueError("oracle_certify: invalid arguments")
+    if r:
+        raise ValidationError(f"certificate fails: {_CERT_WHAT[int(r)]} at vertex {where.value}")
 
 
 def kruskal(row_ptr, col, w):

@@ -164,6 +164,61 @@ int64_t oracle_edges_scanned(int32_t n, const int32_t *row_ptr, const uint32_t *
     return s;
 }
 
+/* Distance certificate: checks that d[] (uint32, 0xFFFFFFFF = unreached) is
+ * exactly the shortest-path distance vector from src over CSR out-edges with
+ * weights w (>= 1; NULL means every weight is 1, i.e. BFS levels), without
+ * computing any distance itself.  With weights >= 1 these three conditions
+ * hold for exactly one vector:
+ *   (i)   d[src] == 0;
+ *   (ii)  every edge u -> v with d[u] finite has d[v] finite and
+ *         d[v] <= d[u] + w  (so d is at most the true distance);
+ *   (iii) every v != src with d[v] finite has an in-edge u -> v with
+ *         d[u] + w == d[v]   (so d is at least the true distance: following
+ *         such edges backwards strictly decreases d and can only stop at src).
+ * One pass over the edges.  Returns 0 when d is certified; otherwise a
+ * positive code (1, 2 or 3 for the condition that fails, 4 for a weight of
+ * 0) and the offending vertex (or edge source) in *where; -1 on invalid
+ * arguments or allocation failure. */
+int64_t oracle_certify(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *w, int32_t src,
+                       const uint32_t *d, int64_t *where) {
+    if (n <= 0 || src < 0 || src >= n || !row_ptr || !col || !d || !where) return -1;
+    *where = -1;
+    if (d[src] != 0) {
+        *where = src;
+        return 1;
+    }
+    unsigned char *tight = (unsigned char *)calloc((size_t)n, 1);
+    if (!tight) return -1;
+    int64_t code = 0;
+    for (int32_t u = 0; u < n && !code; ++u) {
+        if (d[u] == ORACLE_INF) continue;
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col[e];
+            const uint64_t wt = w ? (uint64_t)w[e] : 1u;
+            if (wt == 0) {
+                code = 4;
+                *where = u;
+                break;
+            }
+            const uint64_t cand = (uint64_t)d[u] + wt;
+            if (d[v] == ORACLE_INF || (uint64_t)d[v] > cand) {
+                code = 2;
+                *where = u;
+                break;
+            }
+            if ((uint64_t)d[v] == cand) tight[v] = 1;
+        }
+    }
+    for (int32_t v = 0; v < n && !code; ++v) {
+        if (v != src && d[v] != ORACLE_INF && !tight[v]) {
+            code = 3;
+            *where = v;
+        }
+    }
+    free(tight);
+    return code;
+}
+
 /* ---- minimum spanning forest ------------------------------------------- */
 /*
  * Minimum spanning forest of an undirected graph stored as a symmetric CSR

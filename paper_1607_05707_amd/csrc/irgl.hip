@@ -322,13 +322,24 @@ int fill_grid(uint32_t n, int block) {
     return static_cast<int>(std::max(1u, std::min(g, 65535u)));
 }
 
+// Pinned read-back words of the host-loop mode, one per calling thread, kept
+// in a process-wide registry so that irgl_shutdown() can return them to the
+// HIP runtime while it is still alive (nothing is freed from a static
+// destructor: at process exit the runtime may already be gone).
+std::mutex g_pinned_mu;
+std::vector<void *> g_pinned;
 thread_local uint32_t *t_pinned = nullptr;
+thread_local uint64_t t_pinned_gen = 0;
+uint64_t g_pinned_gen = 1;  // bumped by irgl_shutdown: every thread's word is gone
 
 irgl_status pinned_word(uint32_t **p) {
-    if (!t_pinned) {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!t_pinned || t_pinned_gen != g_pinned_gen) {
         void *h = nullptr;
         IRGL_HIP(hipHostMalloc(&h, 64, hipHostMallocDefault));
         t_pinned = static_cast<uint32_t *>(h);
+        t_pinned_gen = g_pinned_gen;
+        g_pinned.push_back(h);
     }
     *p = t_pinned;
     return IRGL_OK;
@@ -1059,6 +1070,16 @@ irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t
 irgl_status irgl_graph_free(irgl_graph g) {
     delete g;
     return IRGL_OK;
+}
+
+irgl_status irgl_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    irgl_status st = IRGL_OK;
+    for (void *h : g_pinned)
+        if (hipHostFree(h) != hipSuccess) st = hip_fail(hipGetLastError());
+    g_pinned.clear();
+    ++g_pinned_gen;
+    return st;
 }
 
 irgl_status irgl_graph_default_delta(irgl_graph g, uint32_t *delta) {

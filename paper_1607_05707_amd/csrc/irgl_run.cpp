@@ -203,5 +203,6 @@ int main(int argc, char **argv) {
     CK(hipFree(d_col));
     CK(hipFree(d_out));
     if (d_w) CK(hipFree(d_w));
+    CI(irgl_shutdown());
     return 0;
 }

@@ -9,8 +9,10 @@ Importing this module fails loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import torch
@@ -90,6 +92,38 @@ STATS_BYTES = ctypes.sizeof(irgl_stats)
 _c = ctypes.c_void_p
 _lib.irgl_version.restype = ctypes.c_int
 _lib.irgl_version.argtypes = []
+_lib.irgl_shutdown.restype = ctypes.c_int32
+_lib.irgl_shutdown.argtypes = []
+
+# Every live graph, batch and server handle.  At interpreter exit they are
+# released (servers closed, batches and graphs freed) and the library's
+# pinned words returned with irgl_shutdown(), all while the HIP runtime is
+# still up; finalizers that run later find their handles already released.
+_live = weakref.WeakSet()
+_shut = False
+
+
+def _release_all() -> None:
+    global _shut
+    if _shut:
+        return
+    for order in (0, 1, 2):  # servers, then batches, then graphs
+        for h in list(_live):
+            if getattr(h, "_release_order", 2) == order:
+                try:
+                    h._release()
+                except Exception:
+                    pass
+    _lib.irgl_shutdown()
+    _shut = True
+
+
+atexit.register(_release_all)
+
+
+def irgl_shutdown() -> int:
+    """Return the library's process-lifetime host resources (see irgl.h)."""
+    return int(_lib.irgl_shutdown())
 _lib.irgl_status_string.restype = ctypes.c_char_p
 _lib.irgl_status_string.argtypes = [ctypes.c_int32]
 _lib.irgl_last_hip_error.restype = ctypes.c_int32
@@ -206,6 +240,9 @@ class Graph:
         self.w = w
         self.flags = flags
         self.store = store  # device store of a relabelled copy (irgl_graph_upload_reordered)
+        _live.add(self)
+
+    _release_order = 2
 
     @property
     def reordered(self) -> bool:
@@ -216,9 +253,11 @@ class Graph:
         return self.w is not None
 
     def free(self) -> None:
-        if self.handle:
+        if self.handle and not _shut:
             _lib.irgl_graph_free(self.handle)
-            self.handle = None
+        self.handle = None
+
+    _release = free
 
     def __del__(self):
         try:
@@ -538,15 +577,20 @@ def irgl_batch_workspace_bytes(tasks, cfg=None) -> int:
 
 
 class Batch:
+    _release_order = 1
+
     def __init__(self, handle, tasks, ws):
         self.handle = handle
         self.tasks = tasks
         self.ws = ws
+        _live.add(self)
 
     def free(self):
-        if self.handle:
+        if self.handle and not _shut:
             _lib.irgl_batch_free(self.handle)
-            self.handle = None
+        self.handle = None
+
+    _release = free
 
     def __del__(self):
         try:
@@ -622,17 +666,22 @@ def irgl_batch_open_bytes(graphs, cfg=None, ring_cap: int = 256) -> int:
 class Server:
     """An open batch: tasks are enqueued while the server kernel runs."""
 
+    _release_order = 0
+
     def __init__(self, handle, graphs, ws, stream):
         self.handle = handle
         self.graphs = list(graphs)
         self.ws = ws
         self.stream = stream
         self.inflight = {}
+        _live.add(self)
 
     def close(self):
-        if self.handle:
+        if self.handle and not _shut:
             _lib.irgl_batch_close(self.handle)
-            self.handle = None
+        self.handle = None
+
+    _release = close
 
     def __del__(self):
         try:

@@ -210,15 +210,103 @@ def test_uniform_weight_is_scaled_level(oracle_lib):
         np.testing.assert_array_equal(d, exp)
 
 
-def test_histogram_and_edge_count(oracle_lib):
+def test_histogram(oracle_lib):
     g = gg.rmat(12, seed=5)
     rp, c, _ = g.numpy()
     s = gg.pick_sources(g, 1, seed=1)[0]
     lv, _ = oracle.bfs(rp, c, s)
     hist = oracle.level_histogram(lv)
     assert hist[0] == 1 and hist.sum() == int((lv != INF).sum())
-    deg = np.diff(rp)
-    assert oracle.edges_scanned(rp, lv) == int(deg[lv != INF].sum())
+
+
+def test_edges_scanned_closed_forms(oracle_lib):
+    # Every value below is fixed by the graph's shape alone (counted by hand
+    # or by a closed form), not by re-evaluating the oracle's own formula.
+    # (a) a connected symmetric graph: every vertex is reached from any
+    #     source, so every one of its m CSR entries is scanned
+    g64 = gg.config_grid64()
+    rp, c, _ = g64.numpy()
+    assert g64.m == 2 * 2 * 64 * 63 == 16128
+    for s in (0, 1234, 4095):
+        lv, _ = oracle.bfs(rp, c, s)
+        assert oracle.edges_scanned(rp, lv) == 16128
+    # (b) directed path 0 -> 1 -> ... -> n-1 from s: vertices s..n-1 are
+    #     reached and all but the last have one out-edge
+    n = 300
+    gp = gg.from_edges(n, range(n - 1), range(1, n))
+    for s in (0, 17, n - 2, n - 1):
+        lv, _ = oracle.bfs(*gp.numpy()[:2], s)
+        assert oracle.edges_scanned(gp.numpy()[0], lv) == n - 1 - s
+    # (c) an unreachable part: a symmetric star on 0..5 (10 entries), a
+    #     triangle 6, 7, 8 (6 entries) and an isolated vertex 9; from the star
+    #     centre 10 entries, from a triangle corner 6, from 9 none
+    src = [0, 0, 0, 0, 0, 1, 2, 3, 4, 5, 6, 7, 7, 8, 8, 6]
+    dst = [1, 2, 3, 4, 5, 0, 0, 0, 0, 0, 7, 6, 8, 7, 6, 8]
+    gs = gg.from_edges(10, src, dst)
+    rps, cs, _ = gs.numpy()
+    for s, want in ((0, 10), (3, 10), (7, 6), (9, 0)):
+        lv, _ = oracle.bfs(rps, cs, s)
+        assert oracle.edges_scanned(rps, lv) == want, (s, want)
+    # (d) directed cycle of n: all n entries from any source
+    gc = gg.from_edges(97, range(97), [(i + 1) % 97 for i in range(97)])
+    lv, _ = oracle.bfs(*gc.numpy()[:2], 40)
+    assert oracle.edges_scanned(gc.numpy()[0], lv) == 97
+    # (e) a directed out-star 0 -> 1..k plus edges 1 -> 0 back: from leaf 1
+    #     everything is reached (k + 1 entries); from leaf 2, which has no
+    #     out-edge, only 2 itself (0 entries)
+    k = 50
+    go = gg.from_edges(k + 1, [0] * k + [1], list(range(1, k + 1)) + [0])
+    rpo, co, _ = go.numpy()
+    lv, _ = oracle.bfs(rpo, co, 1)
+    assert oracle.edges_scanned(rpo, lv) == k + 1
+    lv, _ = oracle.bfs(rpo, co, 2)
+    assert oracle.edges_scanned(rpo, lv) == 0
+
+
+def test_certificate_accepts_exact_and_rejects_planted_mistakes(oracle_lib):
+    # accepted: the Floyd-Warshall distances of tiny graphs (independent of
+    # Dijkstra) and of medium graphs checked against scipy above
+    checked = 0
+    for g, src in _tiny_graphs():
+        rp, c, w = g.numpy()
+        oracle.certify(rp, c, src, _fw_row(g, src, weighted=True), w)
+        oracle.certify(rp, c, src, _fw_row(g, src, weighted=False))
+        checked += 1
+    assert checked == 320
+    g = gg.uniform_random(3000, 6.0, seed=41, weight_seed=42, wmax=100)
+    rp, c, w = g.numpy()
+    s = gg.pick_sources(g, 1, seed=4)[0]
+    d = _scipy_dist(g, s, weighted=True)
+    lv = _scipy_dist(g, s, weighted=False)
+    oracle.certify(rp, c, s, d, w)
+    oracle.certify(rp, c, s, lv)
+    reached = np.flatnonzero((d != INF) & (np.arange(g.n) != s))
+    rng = np.random.default_rng(5)
+    for v in rng.choice(reached, 20, replace=False):
+        for delta in (-1, 1):
+            bad = d.copy()
+            bad[v] = np.uint32(int(bad[v]) + delta)
+            with pytest.raises(oracle.ValidationError):
+                oracle.certify(rp, c, s, bad, w)
+            badl = lv.copy()
+            badl[v] = np.uint32(int(badl[v]) + delta)
+            with pytest.raises(oracle.ValidationError):
+                oracle.certify(rp, c, s, badl)
+        bad = d.copy()
+        bad[v] = INF
+        with pytest.raises(oracle.ValidationError):
+            oracle.certify(rp, c, s, bad, w)
+    # a distance for a vertex that cannot be reached, and a wrong source value
+    gd = gg.from_edges(4, [0, 1], [1, 2], [5, 5])
+    rpd, cd, wd = gd.numpy()
+    oracle.certify(rpd, cd, 0, np.array([0, 5, 10, INF], dtype=np.uint32), wd)
+    with pytest.raises(oracle.ValidationError):
+        oracle.certify(rpd, cd, 0, np.array([0, 5, 10, 3], dtype=np.uint32), wd)
+    with pytest.raises(oracle.ValidationError):
+        oracle.certify(rpd, cd, 0, np.array([1, 5, 10, INF], dtype=np.uint32), wd)
+    # a whole vector shifted by one everywhere except the source has no tight edge
+    with pytest.raises(oracle.ValidationError):
+        oracle.certify(rpd, cd, 0, np.array([0, 4, 9, INF], dtype=np.uint32), wd)
 
 
 def test_validator_rejects_planted_mistakes(oracle_lib):
