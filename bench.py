@@ -44,8 +44,30 @@ def alg_bytes(kind: int, n: int, reached: int, m_cc: int) -> int:
     return 4 * n + 28 * reached + 12 * m_cc
 
 
-def cpu_baseline(g, sources, budget_s: float, gpu_results):
-    """Time the CPU oracle (one thread) on a bounded sample of the workload."""
+def host_cpu():
+    """CPU model and the threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def cpu_baseline(g, sources, budget_s: float, gpu_results, reps: int = 5):
+    """Time the CPU oracle (one thread) on a bounded sample of the workload:
+    the median of `reps` runs per source and kind, source after source until
+    the budget is spent."""
+    import statistics
+
     import numpy as np
     import oracle
     rp, col, w = g.numpy()
@@ -55,20 +77,24 @@ def cpu_baseline(g, sources, budget_s: float, gpu_results):
     parity = True
     t_start = time.perf_counter()
     for src in sources:
-        t0 = time.perf_counter()
-        lv, _ = oracle.bfs(rp, col, src, with_parent=False)
-        t_bfs += time.perf_counter() - t0
+        runs = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            lv, _ = oracle.bfs(rp, col, src, with_parent=False)
+            runs.append(time.perf_counter() - t0)
+        t_bfs += statistics.median(runs)
         mcc = oracle.edges_scanned(rp, lv)
         e_bfs += mcc
         nb += 1
         if src in gpu_results:
             parity &= bool(np.array_equal(gpu_results[src][0], lv))
-        if time.perf_counter() - t_start > budget_s:
-            break
         if w is not None:
-            t0 = time.perf_counter()
-            d, _ = oracle.dijkstra(rp, col, w, src, with_parent=False)
-            t_sssp += time.perf_counter() - t0
+            runs = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                d, _ = oracle.dijkstra(rp, col, w, src, with_parent=False)
+                runs.append(time.perf_counter() - t0)
+            t_sssp += statistics.median(runs)
             e_sssp += mcc
             ns += 1
             if src in gpu_results:
@@ -76,14 +102,18 @@ def cpu_baseline(g, sources, budget_s: float, gpu_results):
         if time.perf_counter() - t_start > budget_s:
             break
     total_t = t_bfs + t_sssp
+    model, nproc, usable = host_cpu()
     return {
         "value": round((e_bfs + e_sssp) / total_t / 1e9, 4) if total_t > 0 else None,
         "unit": "GTEPS",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{nb} BFS + {ns} SSSP queries (serial queue BFS, binary-heap Dijkstra) "
-                  f"from the first {nb} sources of the same graph, one host thread, "
-                  f"{total_t:.1f} s of CPU time",
+                  f"from the first {nb} sources of the same graph, median of {reps} runs each, "
+                  f"one host thread, {time.perf_counter() - t_start:.1f} s wall",
+        "cpu_model": model,
+        "nproc": nproc,
+        "usable_threads": usable,
         "bfs_gteps": round(e_bfs / t_bfs / 1e9, 4) if t_bfs > 0 else None,
         "sssp_gteps": round(e_sssp / t_sssp / 1e9, 4) if t_sssp > 0 else None,
     }, parity
@@ -201,24 +231,38 @@ def batched_section(args, dev):
             wss[key] = irgl.workspace(hg, kind)
             outs[id(hg)] = torch.empty(hg.n, dtype=torch.int32, device=dev)
     best_plain = float("inf")
+    best_dev = float("inf")
+    stream = torch.cuda.current_stream(dev)
     for _ in range(2):
         torch.cuda.synchronize()
+        evs = []
         t0 = time.perf_counter()
         for hg, kind, src in tasks:
             fn = irgl.irgl_bfs if kind == 0 else irgl.irgl_sssp
-            fn(hg, src, outs[id(hg)], None, wss[(id(hg), kind)])
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn(hg, src, outs[id(hg)], None, wss[(id(hg), kind)], stream)
+            b.record(stream)
+            evs.append((a, b))
         torch.cuda.synchronize()
         best_plain = min(best_plain, time.perf_counter() - t0)
+        best_dev = min(best_dev, sum(a.elapsed_time(b) for a, b in evs) / 1e3)
     total = float(sum(mcc))
-    log(f"batched {t_batch * 1e3:.1f} ms vs plain {best_plain * 1e3:.1f} ms")
+    log(f"batched {t_batch * 1e3:.1f} ms vs plain {best_plain * 1e3:.1f} ms "
+        f"(device time of the plain launches {best_dev * 1e3:.1f} ms)")
     return {"tasks": len(tasks), "config": cfg, "batched_ms": round(t_batch * 1e3, 2),
             "plain_ms": round(best_plain * 1e3, 2), "speedup": round(best_plain / t_batch, 3),
+            "plain_device_ms": round(best_dev * 1e3, 2), "speedup_vs_device": round(best_dev / t_batch, 3),
             "batched_gteps": round(total / t_batch / 1e9, 3), "plain_gteps": round(total / best_plain / 1e9, 3)}
 
 
 def served_section(args, dev):
-    """Continuous batching over the eight resident graphs at a fixed fraction
-    of the plain capacity: p50/p99 latency and throughput, served vs plain."""
+    """Continuous batching over the eight resident graphs.  p50/p99 latency
+    and throughput, served against plain FIFO single launches: a Poisson
+    stream at fractions of the plain capacity, a saturating burst (every
+    query arrives at once: throughput of each form when never idle), and the
+    same burst under a small per-query state budget (admission by memory)."""
     import numpy as np
     from paper_1607_05707_amd import autotune, serve
     t0 = time.perf_counter()
@@ -226,16 +270,116 @@ def served_section(args, dev):
     log(f"served set resident in {time.perf_counter() - t0:.1f}s")
     cap_q = serve.query_stream(graphs, 200, 6)
     capacity = serve.measure_capacity(graphs, cap_q)
-    queries = serve.query_stream(graphs, args.serve_queries, 5)
-    arr = serve.poisson_arrivals(len(queries), args.serve_lambda * capacity, 12)
     cfg = autotune.load("serve")
-    lat_s, wall_s, _, rej = serve.run_served(graphs, queries, arr, 4 << 30, cfg=cfg)
-    lat_p, wall_p = serve.run_plain(graphs, queries, arr)
-    out = {"graphs": len(graphs), "queries": len(queries), "lambda_frac": args.serve_lambda, "config": cfg,
-           "plain_capacity_qps": round(capacity, 1), "budget_gb": 4, "rejected": rej,
-           "served": serve.summarize(lat_s, wall_s), "plain": serve.summarize(lat_p, wall_p)}
-    log(f"served {out['served']} plain {out['plain']}")
-    return out
+    budget = 4 << 30
+    sweep = {}
+    for frac in [float(x) for x in args.serve_lambdas.split(",")]:
+        queries = serve.query_stream(graphs, args.serve_queries, 5)
+        arr = serve.poisson_arrivals(len(queries), frac * capacity, 12)
+        info = {}
+        lat_s, wall_s, _, rej = serve.run_served(graphs, queries, arr, budget, cfg=cfg, info=info)
+        lat_p, wall_p = serve.run_plain(graphs, queries, arr)
+        sweep[str(frac)] = {"served": serve.summarize(lat_s, wall_s), "plain": serve.summarize(lat_p, wall_p),
+                            "rejected": rej, **info}
+        log(f"served lambda={frac}: {sweep[str(frac)]}")
+    queries = serve.query_stream(graphs, args.serve_burst, 7)
+    burst = np.zeros(len(queries))
+    info = {}
+    lat_s, wall_s, _, rej = serve.run_served(graphs, queries, burst, budget, cfg=cfg, info=info)
+    lat_p, wall_p = serve.run_plain(graphs, queries, burst)
+    saturating = {"queries": len(queries), "served": serve.summarize(lat_s, wall_s),
+                  "plain": serve.summarize(lat_p, wall_p), "rejected": rej, **info}
+    saturating["qps_ratio"] = round(saturating["served"]["qps"] / saturating["plain"]["qps"], 3)
+    log(f"served saturating burst: {saturating}")
+    small_budget = args.serve_small_budget_mb << 20
+    info = {}
+    lat_m, wall_m, _, rej_m = serve.run_served(graphs, queries, burst, small_budget, cfg=cfg, info=info)
+    memory_bound = {"budget_mb": args.serve_small_budget_mb, "served": serve.summarize(lat_m, wall_m),
+                    "rejected": rej_m, **info}
+    log(f"served under a {args.serve_small_budget_mb} MiB state budget: {memory_bound}")
+    return {"graphs": len(graphs), "config": cfg, "plain_capacity_qps": round(capacity, 1), "budget_gb": 4,
+            "queries_per_lambda": args.serve_queries, "lambda_sweep": sweep, "saturating": saturating,
+            "memory_bound": memory_bound}
+
+
+def level_section(dev, stream, name, reps=2):
+    """Barrier-bound workloads: one BFS and one SSSP from source 0, time per
+    invocation (the outlined loop's cost per level) and per query."""
+    import torch
+    from paper_1607_05707_amd import irgl
+    from paper_1607_05707_amd.workloads import make_workload
+    g = make_workload(name, dev, 1)
+    hg = irgl.upload(g, reorder=True)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    stats = irgl.stats_tensor(dev)
+    res = {"n": g.n, "m": g.m}
+    for k, fn in ((0, irgl.irgl_bfs), (1, irgl.irgl_sssp)):
+        ws = irgl.workspace(hg, k)
+        fn(hg, 0, out, None, ws, stream, stats)  # warm
+        best = float("inf")
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn(hg, 0, out, None, ws, stream, stats)
+            b.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b))
+        st = irgl.read_stats(stats)
+        if st["status"] != 0:
+            raise SystemExit(f"{name} kind {k} failed: {irgl.irgl_status_string(st['status'])}")
+        res[["bfs", "sssp"][k]] = {"query_us": round(best * 1e3, 1), "invocations": st["iterations"],
+                                   "us_per_invocation": round(best * 1e3 / max(1, st["iterations"]), 2)}
+    log(f"{name}: {res}")
+    del hg
+    return res
+
+
+def road_section(dev, stream, reps=2):
+    """The road-like 4096 x 4096 grid with its long edges: BFS and SSSP from
+    its 9 sources, GTEPS and the fraction of the HBM roofline per kind."""
+    import torch
+    from paper_1607_05707_amd import irgl
+    from paper_1607_05707_amd.workloads import make_workload
+    g = make_workload("road4096", dev, 9)
+    hg = irgl.upload(g, reorder=True)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    stats = irgl.stats_tensor(dev)
+    res = {"n": g.n, "m": g.m, "sources": len(g.sources)}
+    mcc, reached = {}, {}
+    ws0 = irgl.workspace(hg, 0)
+    for s in g.sources:
+        irgl.irgl_bfs(hg, s, out, None, ws0, stream, stats)
+        st = irgl.read_stats(stats)
+        mcc[s], reached[s] = st["frontier_edges"], st["items"]
+    for k, fn in ((0, irgl.irgl_bfs), (1, irgl.irgl_sssp)):
+        ws = irgl.workspace(hg, k)
+        tot = 0.0
+        for s in g.sources:
+            fn(hg, s, out, None, ws, stream, stats)  # warm
+            best = float("inf")
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn(hg, s, out, None, ws, stream, stats)
+                b.record(stream)
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b))
+            st = irgl.read_stats(stats)
+            if st["status"] != 0:
+                raise SystemExit(f"road4096 kind {k} from {s} failed: {irgl.irgl_status_string(st['status'])}")
+            tot += best
+        nq = len(g.sources)
+        alg = sum(alg_bytes(k, g.n, reached[s], mcc[s]) for s in g.sources) / nq
+        avg_ms = tot / nq
+        res[["bfs", "sssp"][k]] = {"avg_query_us": round(avg_ms * 1e3, 1),
+                                   "gteps": round(sum(mcc.values()) / (tot / 1e3) / 1e9, 3),
+                                   "alg_bytes_per_query": int(alg),
+                                   "roofline_frac": round(alg / (avg_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    log(f"road4096: {res}")
+    del hg
+    return res
 
 
 def main() -> int:
@@ -264,8 +408,11 @@ def main() -> int:
     ap.add_argument("--no-mst", action="store_true")
     ap.add_argument("--topology-sources", type=int, default=8)
     ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--serve-lambda", type=float, default=0.8)
+    ap.add_argument("--serve-queries", type=int, default=400, help="queries per point of the lambda sweep")
+    ap.add_argument("--serve-lambdas", default="0.25,0.5,0.8,0.95")
+    ap.add_argument("--serve-burst", type=int, default=600)
+    ap.add_argument("--serve-small-budget-mb", type=int, default=96)
+    ap.add_argument("--no-levels", action="store_true", help="skip the grid64 / road4096 legs")
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="first copy this many MiB device to device once (a copy of known traffic that "
                          "scales hardware byte counters)")
@@ -335,16 +482,23 @@ def main() -> int:
             gpu_results[s] = (lv, d)
     log(f"m_cc: mean {sum(mcc.values()) / len(mcc):.0f} over {len(mcc)} sources")
 
-    def one_step(record):
+    # every timed query writes its own statistics block, so that a failure of
+    # any one of them (not only the last) fails the bench
+    nq_step = len(sources) * len(kinds)
+    qstats = torch.zeros((args.steps * nq_step, irgl.STATS_BYTES), dtype=torch.uint8, device=dev)
+
+    def one_step(record, step=0):
+        q = step * nq_step
         for s in sources:
             for k in kinds:
                 if record is not None:
                     a = torch.cuda.Event(enable_timing=True)
                     b = torch.cuda.Event(enable_timing=True)
                     a.record(stream)
-                    fns[k](hg, s, out, None, ws[k], stream, None, cfg)
+                    fns[k](hg, s, out, None, ws[k], stream, qstats[q], cfg)
                     b.record(stream)
-                    record.append((k, s, a, b))
+                    record.append((k, s, a, b, q))
+                    q += 1
                 else:
                     fns[k](hg, s, out, None, ws[k], stream, None, cfg)
 
@@ -357,21 +511,22 @@ def main() -> int:
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        one_step(events)
+        one_step(events, i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     log(f"timed {args.steps} steps in {elapsed:.3f}s")
 
-    # status of the last queries: the timed calls pass no stats block
-    for k in kinds:
-        st = irgl.irgl_query_status(ws[k], stream)
-        if st["status"] != 0:
-            raise SystemExit(f"kind {k} failed: {irgl.irgl_status_string(st['status'])}")
-
     names_k = {0: "bfs", 1: "sssp"}
+    all_stats = irgl.read_stats_array(qstats)
+    bad = [(names_k[k], s, st["status"]) for (k, s, _, _, q), st in zip(events, all_stats) if st["status"] != 0]
+    if bad:
+        raise SystemExit(f"{len(bad)} timed queries failed, first: {bad[0][0]} from {bad[0][1]}: "
+                         f"{irgl.irgl_status_string(bad[0][2])}")
     per_kind_ms = {k: [] for k in kinds}
-    for k, s, a, b in events:
+    per_kind_edges = {k: 0 for k in kinds}
+    for (k, s, a, b, q), st in zip(events, all_stats):
         per_kind_ms[k].append(a.elapsed_time(b))
+        per_kind_edges[k] += st["edges"]
     teps_edges = args.steps * sum(mcc[s] for s in sources) * len(kinds)
     value = teps_edges / elapsed / 1e9
 
@@ -387,6 +542,8 @@ def main() -> int:
             "avg_query_us": round(avg_ms * 1e3, 1),
             "alg_bytes_per_query": int(bytes_per_query),
             "alg_gbs": round(bytes_per_query / (avg_ms / 1e3) / 1e9, 1),
+            # CSR entries the kernel scanned per entry of the reached component
+            "scans_per_edge": round(per_kind_edges[k] / edges, 3),
             "total_ms": tot_ms,
         }
     dom = max(kinds, key=lambda k: kind_summary[k]["total_ms"])
@@ -432,6 +589,12 @@ def main() -> int:
     if not args.no_served:
         served = served_section(args, dev)
 
+    levels = None
+    if not args.no_levels:
+        levels = {"grid64": level_section(dev, stream, "grid64"),
+                  "road4096_nolong": level_section(dev, stream, "road4096_nolong", reps=1),
+                  "road4096": road_section(dev, stream)}
+
     names = {0: "bfs", 1: "sssp"}
     line = {
         "metric": "GTEPS BFS/SSSP on RMAT-22, batched vs plain; HBM GB/s; p99 query latency",
@@ -466,6 +629,7 @@ def main() -> int:
         "served": served,
         "topology": topology,
         "mst": mst,
+        "levels": levels,
     }
     print(json.dumps(line), flush=True)
     return 0

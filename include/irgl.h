@@ -167,9 +167,13 @@ typedef struct irgl_config {
                              a graph uploaded with IRGL_VALIDATE (mean weight W,
                              mean out-degree D, largest out-degree X): D < 8:
                              32 W / D; D >= 8 and X <= 16 D: 16 W / D; D >= 8,
-                             X > 16 D and at least 2^26 edges: W; otherwise (and
-                             without IRGL_VALIDATE) IRGL_DELTA_NONE (plain
-                             Bellman-Ford order) */
+                             X > 16 D and at least 2^26 edges: W (W / 2 on a
+                             relabelled upload, whose SSSP copy is partitioned
+                             into light and heavy edges at that step);
+                             otherwise (and without IRGL_VALIDATE)
+                             IRGL_DELTA_NONE (plain Bellman-Ford order).  A
+                             vertex whose distance has not changed since its
+                             last expansion is not expanded again */
     uint64_t *trace;      /* DEVICE uint64[trace_len], zeroed by the caller, or NULL.
                              Twelve words per invocation i at 12i: wall-clock tick at
                              its start, incoming worklist size, edges scanned, vertices
@@ -181,7 +185,8 @@ typedef struct irgl_config {
                              12 x iterations.  In persistent mode top-down
                              invocations fill every word, bottom-up invocations
                              all but the busy ticks, and SSSP far-to-near transfer
-                             invocations only the first two; in host-loop mode
+                             invocations only the first two (on a partitioned
+                             graph also the heavy pass they run: words 2-10); in host-loop mode
                              every invocation writes its first two words;
                              topology-driven launches record no trace */
     uint32_t barrier;     /* grid-barrier coherence scheme: IRGL_BARRIER_XCD (default:
@@ -254,17 +259,37 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out);
  * as there), builds the copy in `store` (DEVICE, at least
  * irgl_reorder_bytes, borrowed until irgl_graph_free, like the CSR arrays,
  * which also stay borrowed) on the current device's null stream, and
- * synchronizes.  IRGL_ERR_WORKSPACE_TOO_SMALL when store_bytes is short. */
+ * synchronizes.  IRGL_ERR_WORKSPACE_TOO_SMALL when store_bytes is short.
+ *
+ * A weighted graph also gets an SSSP copy whose rows are partitioned at the
+ * graph's default near/far step: edges lighter than the step first, then
+ * the heavy ones (each part in id order).  Single SSSP queries that use that
+ * step expand only light edges when a vertex is popped and relax each heavy
+ * edge once, with the vertex's final distance, after its bucket has drained
+ * (the light/heavy split of bucketed shortest paths); results are the same
+ * as without it.  irgl_reorder_bytes counts this copy (8 bytes per edge and
+ * 4 per vertex more for a weighted graph). */
 irgl_status irgl_reorder_bytes(int32_t n, int64_t m, int32_t weighted, size_t *bytes);
 irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t store_bytes, irgl_graph *out);
+
+/* Change the SSSP near/far step that single queries on g take when their
+ * configuration leaves delta at 0 (IRGL_DELTA_NONE: plain Bellman-Ford
+ * order).  On a relabelled weighted graph the light/heavy partition of its
+ * SSSP copy is rebuilt for the new step on the graph's device (synchronous).
+ * Must not run while a query on g is in flight.  Batched and served tasks
+ * keep the rule given at irgl_config.delta.
+ * Errors: INVALID_ARGUMENT (null g, delta 0), DEVICE. */
+irgl_status irgl_graph_set_delta(irgl_graph g, uint32_t delta);
 
 /* Release a handle (not the arrays it borrows).  NULL is accepted. */
 irgl_status irgl_graph_free(irgl_graph g);
 
 /* The SSSP near/far step that a query on g uses when its configuration leaves
  * delta at 0 (the rule is given at irgl_config.delta; the mean weight, mean
- * and largest out-degree come from the upload's IRGL_VALIDATE pass).  *delta
- * receives IRGL_DELTA_NONE for plain Bellman-Ford order.  No device work.
+ * and largest out-degree come from the upload's IRGL_VALIDATE pass; a graph
+ * with a partitioned SSSP copy takes its partition step, and
+ * irgl_graph_set_delta changes it).  *delta receives IRGL_DELTA_NONE for
+ * plain Bellman-Ford order.  No device work.
  * Errors: INVALID_ARGUMENT (null g or delta). */
 irgl_status irgl_graph_default_delta(irgl_graph g, uint32_t *delta);
 
@@ -364,6 +389,141 @@ irgl_status irgl_batch_wait(irgl_batch b, irgl_stats *per_task);
 
 /* Release the handle (waits for the batch first). */
 irgl_status irgl_batch_free(irgl_batch b);
+
+/* ---------------------------------------------------------------------
+ * Pipes (Section 4.2, Compiling Pipe; Section 4.3, Compiling Kernel
+ * Invocations).  A pipe program is a list of orchestration statements over
+ * the library's kernel bodies, run by ONE outlined control kernel (a
+ * cooperative persistent launch; every invocation is a device-function call
+ * followed by a grid barrier).  All statements share the pipe context: the
+ * incoming, outgoing and retry worklists `in`, `out`, `retry` (each of n
+ * vertex ids).  An invocation of a body that uses worklists pops `in` and
+ * pushes `out` (with cooperative conversion); afterwards `in` and `out` are
+ * swapped.  A body that also uses `retry` is invoked again, with `in` and
+ * `retry` swapped and `out` kept, while its retry list is non-empty; then
+ * `in` and `out` are swapped.  A body that uses no worklist leaves them as
+ * they are.
+ *
+ * Statements (irgl_pipe_op.op; a, b are arguments):
+ *   IRGL_PIPE_INVOKE  a = body: one invocation (Invoke)
+ *   IRGL_PIPE_ITERATE a = body: invocations until its worklist is empty, or,
+ *                     for a body that returns a reduction, until it returns
+ *                     false (Iterate)
+ *   IRGL_PIPE_BEGIN   a = 0: a looping Pipe (its statements repeat while
+ *                     `in` is non-empty at its END), a = 1: Pipe Once
+ *   IRGL_PIPE_END     closes the innermost BEGIN
+ *   IRGL_PIPE_IF      a = condition, b = the statement to continue at when it
+ *                     is false (forward only): the consumer of a worklist is
+ *                     chosen at run time (dynamic piping)
+ *   IRGL_PIPE_JUMP    a = statement to continue at (forward only)
+ *   IRGL_PIPE_INIT_SOURCE  `in` = [io->src] (the scalar worklist initializer);
+ *                     BFS levels are reset to INF except level[src] = 0
+ * Conditions: IRGL_COND_IN_EMPTY (`in` is empty), IRGL_COND_FRONTIER_LARGE
+ * (`in` holds at least n / 16 vertices), IRGL_COND_RETURNED (the last
+ * reduction returned true); IRGL_COND_NOT (or'ed in) negates.
+ *
+ * T_control (Section 4.3): each body has a set T_k of workgroup sizes it can
+ * run with, from its class (ElasticBlock: any size up to the launch bound
+ * of 1024; ShrinkableBlock: up to `block`; FixedBlock: exactly `block`) and
+ * its LDS footprint (lds_base + lds_per_thread x size must fit the device's
+ * per-workgroup LDS).  The control kernel of a program runs with the largest
+ * size in the intersection of its bodies' sets; an empty intersection means
+ * the pipe cannot be outlined (IRGL_ERR_CONFIG).  Sizes are powers of two
+ * from 64 to 1024.
+ * --------------------------------------------------------------------- */
+enum {
+    IRGL_PIPE_INVOKE = 0,
+    IRGL_PIPE_ITERATE = 1,
+    IRGL_PIPE_BEGIN = 2,
+    IRGL_PIPE_END = 3,
+    IRGL_PIPE_IF = 4,
+    IRGL_PIPE_JUMP = 5,
+    IRGL_PIPE_INIT_SOURCE = 6
+};
+enum { IRGL_COND_IN_EMPTY = 0, IRGL_COND_FRONTIER_LARGE = 1, IRGL_COND_RETURNED = 2 };
+#define IRGL_COND_NOT 0x100
+
+/* Kernel bodies a program may invoke. */
+enum {
+    IRGL_BODY_BFS_PUSH = 0,     /* top-down BFS level: pops `in`, labels unvisited out-neighbours
+                                   with the next level, pushes them (nested edge parallelism) */
+    IRGL_BODY_BFS_PULL = 1,     /* bottom-up BFS level (symmetric graphs): every unvisited vertex
+                                   with a neighbour in the current level is labelled and pushed */
+    IRGL_BODY_MST_INIT = 2,     /* Boruvka: every vertex its own component; pushes the vertices
+                                   that have edges (worklist initializer from an array) */
+    IRGL_BODY_MST_FINDMIN = 3,  /* pops `in`: a vertex's lightest edge to another component becomes
+                                   the component's candidate inside a non-blocking Atomic section;
+                                   the vertex is pushed to `out` when it had such an edge, or to
+                                   `retry` when the section's lock was busy (Atomic ... Else) */
+    IRGL_BODY_MST_HOOK = 4,     /* every component root hooks to the component at the other end of
+                                   its candidate edge, which joins the forest */
+    IRGL_BODY_MST_JUMP = 5,     /* pointer jumping over the hooks; returns Any(changed) */
+    IRGL_BODY_MST_RELABEL = 6,  /* every vertex moves to its component's new root */
+    IRGL_BODY_MST_MINID = 7,    /* smallest vertex id of every component */
+    IRGL_BODY_MST_LABEL = 8,    /* component[v] = that smallest id */
+    IRGL_BODY_COUNT = 9
+};
+
+#define IRGL_BLOCK_ELASTIC 0
+#define IRGL_BLOCK_SHRINKABLE 1
+#define IRGL_BLOCK_FIXED 2
+
+typedef struct irgl_block_constraint {
+    int32_t kind;            /* IRGL_BLOCK_* */
+    int32_t block;           /* ShrinkableBlock: largest size; FixedBlock: the size; Elastic: ignored */
+    int32_t lds_base;        /* LDS bytes per workgroup ... */
+    int32_t lds_per_thread;  /* ... plus this many per thread */
+} irgl_block_constraint;
+
+typedef struct irgl_pipe_op {
+    int32_t op;
+    int32_t a;
+    int32_t b;
+    int32_t reserved;
+} irgl_pipe_op;
+
+typedef struct irgl_pipe_io {
+    int32_t src;             /* source of IRGL_PIPE_INIT_SOURCE */
+    uint32_t *level;         /* BFS bodies: DEVICE uint32[n] (output) */
+    int32_t *component;      /* MST bodies: DEVICE int32[n] (output: smallest vertex id of the tree) */
+    uint8_t *in_forest;      /* MST bodies: DEVICE uint8[m] (output: 1 on both entries of forest edges) */
+    uint64_t *weight;        /* MST bodies: DEVICE uint64[1] (output: forest weight) */
+    int32_t *trace;          /* DEVICE int32[trace_len] or NULL: the body of each invocation */
+    uint32_t trace_len;
+    int32_t block;           /* 0 = the largest size of T_control; else a member of it */
+    uint32_t max_invocations; /* safety cap (0 = 8 n + 64): IRGL_ERR_ITERATION_LIMIT */
+    uint32_t watchdog_ms;    /* 0 = 20000 */
+    int32_t grid;            /* workgroups (0 = co-resident limit) */
+    uint32_t force_retry;    /* test knob: 1 = in the first round of every MST_FINDMIN invocation
+                                the vertices with odd ids take the Else branch (retry) as if
+                                their lock were busy; results are unchanged */
+} irgl_pipe_io;
+
+/* T_control of a set of constraints for a per-workgroup LDS limit (bytes):
+ * the largest power-of-two size in [64, 1024] that every constraint admits,
+ * or IRGL_ERR_CONFIG when none does.  Host-only. */
+irgl_status irgl_control_block(const irgl_block_constraint *k, int32_t nk, int32_t lds_limit, int32_t *block);
+/* The constraint of a library body (from its launch bound and LDS layout).  Host-only. */
+irgl_status irgl_pipe_body_constraint(int32_t body, irgl_block_constraint *out);
+/* Structural check of a program: known statements, conditions and bodies,
+ * balanced BEGIN/END (at most 8 deep), forward targets in range, ITERATE of
+ * bodies that use a worklist or return a reduction, and at least one
+ * invocation inside every looping Pipe.  Host-only (IRGL_ERR_INVALID_ARGUMENT). */
+irgl_status irgl_pipe_check(const irgl_pipe_op *prog, int32_t nops);
+/* T_control of a program's bodies; lds_limit 0 = the current device's. */
+irgl_status irgl_pipe_control_block(const irgl_pipe_op *prog, int32_t nops, int32_t requested, int32_t lds_limit,
+                                    int32_t *block);
+/* Device workspace bytes of a program on g. */
+irgl_status irgl_pipe_workspace_bytes(irgl_graph g, const irgl_pipe_op *prog, int32_t nops, size_t *bytes);
+/* Run a program on g (caller's vertex ids) asynchronously on `stream`; the
+ * program is copied during the call.  The outputs a program's bodies need
+ * must be given in io (INVALID_ARGUMENT otherwise); BFS_PULL and the MST
+ * bodies need a symmetric graph (IRGL_SYMMETRIC; CONFIG otherwise), the MST
+ * bodies weights (NO_WEIGHTS).  Device-side errors are in dstats->status.
+ * stats: iterations = invocations, items = popped worklist items, edges =
+ * scanned CSR entries, max_frontier = largest `in`. */
+irgl_status irgl_pipe_run(irgl_graph g, const irgl_pipe_op *prog, int32_t nops, const irgl_pipe_io *io, void *ws,
+                          size_t ws_bytes, void *stream, irgl_stats *dstats);
 
 /* ---------------------------------------------------------------------
  * Open batches (serving): the teams of a persistent server kernel take

@@ -74,7 +74,19 @@ struct irgl_graph_s {
     const uint32_t *orig_w;
     // degree-sorted relabelling (irgl_graph_upload_reordered), else null / empty
     const int32_t *perm;           // device: internal id -> caller id
+    const int32_t *inv;            // device: caller id -> internal id
     std::vector<int32_t> inv_host;  // host: caller id -> internal id
+    // SSSP copy of a relabelled weighted graph (null otherwise): the rows of
+    // (col, w) partitioned into the edges lighter than split_delta, then the
+    // rest, each part in id order; split[v] = first heavy edge of row v.
+    // `split` is null when no edge is heavy (the partition would be unused).
+    int32_t *scol = nullptr;
+    uint32_t *sw = nullptr;
+    int32_t *split_store = nullptr;
+    const int32_t *split = nullptr;
+    uint32_t split_delta = IRGL_DELTA_NONE;
+    // SSSP near/far step of single queries that leave it at 0
+    uint32_t qdelta = IRGL_DELTA_NONE;
 };
 
 namespace {
@@ -122,6 +134,11 @@ constexpr double kSkew = 16.0;
 constexpr int64_t kDeltaSkewMinEdges = int64_t(1) << 26;
 
 uint32_t default_delta(const irgl_graph_s *g);
+uint32_t delta_rule(const irgl_graph_s *g, bool partitioned);
+// Step of the light/heavy partition on a scale-free graph, as a fraction of
+// the mean weight: each heavy edge is then relaxed once, while a smaller
+// step adds buckets (one barrier each).
+constexpr double kSplitDeltaScale = 0.5;
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Per-device facts, looked up once.
@@ -248,10 +265,16 @@ uint32_t grid_list_cap(int64_t n, int64_t m, int t_grid, int block) {
 }
 
 struct Layout {
-    size_t ctrl, wl0, wl1, stamp, shadow, far0, far1, far_flag, visited, frontier, hub_v, hub_base, rval, rparent,
-        total;
+    size_t ctrl, wl0, wl1, stamp, shadow, far0, far1, far_flag, expd, hlist, hstamp, visited, frontier, hub_v,
+        hub_base, rval, rparent, total;
     uint32_t hub_cap;
 };
+
+// An SSSP query runs the light/heavy split when the graph has a partition at
+// the query's step and the loop is outlined.
+bool uses_split(const irgl_graph_s *g, int kind, const Cfg &c) {
+    return kind == IRGL_KIND_SSSP && g->split && c.delta == g->split_delta && c.mode == IRGL_MODE_PERSISTENT;
+}
 
 Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     Layout L;
@@ -265,7 +288,11 @@ Layout layout(const irgl_graph_s *g, int kind, const Cfg &c, bool with_parent) {
     L.far0 = L.shadow + (sssp ? nb : 0);
     L.far1 = L.far0 + (sssp ? nb : 0);
     L.far_flag = L.far1 + (sssp ? nb : 0);
-    L.visited = L.far_flag + (sssp ? nb : 0);
+    L.expd = L.far_flag + (sssp ? nb : 0);
+    const bool split = uses_split(g, kind, c);
+    L.hlist = L.expd + (sssp ? nb : 0);
+    L.hstamp = L.hlist + (split ? nb : 0);
+    L.visited = L.hstamp + (split ? nb : 0);
     const size_t bm = align_up((static_cast<size_t>(g->n) + 31) / 32 * 4);
     const bool pull = kind == IRGL_KIND_BFS && c.do_alpha != 0;
     const bool bitmap = c.t_bitmap != IRGL_BITMAP_NEVER || pull;
@@ -284,8 +311,12 @@ struct OccEntry {
     const void *kernel;
     int block, dev, per_cu;
 };
+// Fixed-capacity cache (no heap growth on the launch path); when it is full
+// the query is simply not cached.
+constexpr int kOccCap = 256;
 std::mutex g_occ_mu;
-std::vector<OccEntry> g_occ;
+OccEntry g_occ[kOccCap];
+int g_occ_n = 0;
 
 template <class K>
 irgl_status coresident_grid(K kernel, int block, int dev, int requested, int *grid) {
@@ -297,13 +328,15 @@ irgl_status coresident_grid(K kernel, int block, int dev, int requested, int *gr
     const void *key = reinterpret_cast<const void *>(kernel);
     {
         std::lock_guard<std::mutex> lk(g_occ_mu);
-        for (const OccEntry &e : g_occ)
+        for (int i = 0; i < g_occ_n; ++i) {
+            const OccEntry &e = g_occ[i];
             if (e.kernel == key && e.block == block && e.dev == dev) per_cu = e.per_cu;
+        }
     }
     if (per_cu < 0) {
         IRGL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0));
         std::lock_guard<std::mutex> lk(g_occ_mu);
-        g_occ.push_back(OccEntry{key, block, dev, per_cu});
+        if (g_occ_n < kOccCap) g_occ[g_occ_n++] = OccEntry{key, block, dev, per_cu};
     }
     // Measured on gfx950: a grid that fills 7 waves per SIMD is not fully
     // co-resident (the barrier then waits for workgroups that never start),
@@ -478,6 +511,14 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.row_ptr = g->row_ptr;
     p.col = g->col;
     p.w = g->w;
+    if (uses_split(g, kind, c)) {
+        p.col = g->scol;
+        p.w = g->sw;
+        p.split = g->split;
+        p.hlist = reinterpret_cast<int32_t *>(base + L.hlist);
+        p.hstamp = reinterpret_cast<uint32_t *>(base + L.hstamp);
+        p.hcap = static_cast<uint32_t>(g->n);
+    }
     p.val = g->perm ? reinterpret_cast<uint32_t *>(base + L.rval) : out;
     p.parent = g->perm && parent ? reinterpret_cast<int32_t *>(base + L.rparent) : parent;
     p.perm = g->perm;
@@ -501,6 +542,7 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
         p.far1 = reinterpret_cast<int32_t *>(base + L.far1);
         p.far_flag = reinterpret_cast<uint32_t *>(base + L.far_flag);
         p.far_cap = static_cast<uint32_t>(g->n);
+        p.expd = reinterpret_cast<uint32_t *>(base + L.expd);
     }
     p.delta = c.delta;
     p.thresh = c.delta;
@@ -519,9 +561,18 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
     p.src = g->perm ? g->inv_host[static_cast<size_t>(src)] : src;
     p.src_orig = src;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // Relabelled graph: the outlined loop maps its results back to caller ids
+    // itself at the end of the launch, unless an SSSP parent pass must run
+    // after it (then a separate kernel maps them back afterwards).
+    const bool fused_map = g->perm && c.mode == IRGL_MODE_PERSISTENT && !(kind == IRGL_KIND_SSSP && parent);
+    if (fused_map) {
+        p.inv = g->inv;
+        p.out_caller = out;
+        p.parent_caller = parent;
+    }
     if (kind == IRGL_KIND_BFS) st = dispatch_block<BfsOp>(g, p, c, s, kind);
     else st = dispatch_block<SsspOp>(g, p, c, s, kind);
-    if (st == IRGL_OK && g->perm) {
+    if (st == IRGL_OK && g->perm && !fused_map) {
         hipLaunchKernelGGL(scatter_results_kernel, dim3(fill_grid(g->n, 256)), dim3(256), 0, s, g->n, g->perm,
                            p.val, p.parent, out, parent);
         if (hipGetLastError() != hipSuccess) st = hip_fail(hipGetLastError());
@@ -538,7 +589,7 @@ struct BatchLayout {
     size_t queue, team_task, tasks, stats, scratch, total;
     size_t team_bytes;
     size_t off_wl0, off_wl1, off_stamp, off_shadow, off_far0, off_far1, off_far_flag, off_visited, off_hub_v,
-        off_hub_base;
+        off_hub_base, off_expd;
     uint32_t cap, hub_cap;
     int teams;
     int team;  // workgroups per team
@@ -617,6 +668,7 @@ void region_layout(int64_t nmax, int64_t mmax, bool any_sssp, int t_grid, int bl
     L->off_far0 = o;  o += any_sssp ? nb : 0;
     L->off_far1 = o;  o += any_sssp ? nb : 0;
     L->off_far_flag = o;  o += any_sssp ? nb : 0;
+    L->off_expd = o;  o += any_sssp ? nb : 0;
     L->off_visited = o;  o += align_up((static_cast<size_t>(nmax) + 31) / 32 * 4);
     L->off_hub_v = o;  o += align_up(static_cast<size_t>(L->hub_cap) * 4);
     L->off_hub_base = o;  o += align_up(static_cast<size_t>(L->hub_cap) * 4);
@@ -746,6 +798,7 @@ void fill_batch_params(BatchParams &bp, const BatchLayout &L, char *base, const 
     bp.off_far0 = L.off_far0;
     bp.off_far1 = L.off_far1;
     bp.off_far_flag = L.off_far_flag;
+    bp.off_expd = L.off_expd;
     bp.off_visited = L.off_visited;
     bp.off_hub_v = L.off_hub_v;
     bp.off_hub_base = L.off_hub_base;
@@ -767,12 +820,17 @@ irgl_status launch_server(const ServerParams &sp, int grid, hipStream_t s) {
     return IRGL_OK;
 }
 
+// Batched and served tasks traverse the caller's rows (no partition).
 uint32_t task_delta(const irgl_graph_s *g, uint32_t override_delta) {
-    return override_delta ? override_delta : default_delta(g);
+    return override_delta ? override_delta : delta_rule(g, false);
 }
 
+// Single queries that leave the step at 0.
+uint32_t default_delta(const irgl_graph_s *g) { return g->qdelta; }
+
 // The mean weight is known when the upload validated the graph.
-uint32_t default_delta(const irgl_graph_s *g) {
+// `partitioned`: rows are split into light and heavy edges at the step.
+uint32_t delta_rule(const irgl_graph_s *g, bool partitioned) {
     if (!g->weight_sum || g->m <= 0 || g->n <= 0) return IRGL_DELTA_NONE;
     const double mean_w = static_cast<double>(g->weight_sum) / static_cast<double>(g->m);
     const double mean_deg = static_cast<double>(g->m) / static_cast<double>(g->n);
@@ -783,7 +841,7 @@ uint32_t default_delta(const irgl_graph_s *g) {
         d = kDeltaDenseScale * mean_w / mean_deg;
     } else {
         if (g->m < kDeltaSkewMinEdges) return IRGL_DELTA_NONE;
-        d = mean_w;
+        d = partitioned ? kSplitDeltaScale * mean_w : mean_w;
     }
     return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
 }
@@ -791,11 +849,80 @@ uint32_t default_delta(const irgl_graph_s *g) {
 __device__ uint32_t g_invalid_flag;
 __device__ unsigned long long g_weight_sum;
 __device__ uint32_t g_max_degree;
+__device__ unsigned long long g_heavy_edges;
 
 __global__ void clear_flag_kernel() {
     g_invalid_flag = 0u;
     g_weight_sum = 0ull;
     g_max_degree = 0u;
+    g_heavy_edges = 0ull;
+}
+
+// Light/heavy partition of every row (upload time): one wavefront per row
+// counts the edges lighter than `delta`, then writes them, in row order, in
+// front of the others (also in row order); split[v] = first heavy edge.
+__global__ void partition_rows_kernel(int32_t n, const int32_t *rp, const int32_t *col, const uint32_t *w,
+                                      uint32_t delta, int32_t *scol, uint32_t *sw, int32_t *split,
+                                      unsigned long long *heavy_total) {
+    const int lane = threadIdx.x % kWave;
+    const int32_t waves = static_cast<int32_t>(gridDim.x * (blockDim.x / kWave));
+    unsigned long long heavy = 0;
+    for (int32_t u = static_cast<int32_t>(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave); u < n;
+         u += waves) {
+        const int32_t r0 = rp[u], r1 = rp[u + 1];
+        int32_t nl = 0;
+        for (int32_t e0 = r0; e0 < r1; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            nl += __popcll(__ballot(e < r1 && w[e] < delta));
+        }
+        int32_t lo = r0, hi = r0 + nl;
+        for (int32_t e0 = r0; e0 < r1; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            const bool in = e < r1;
+            const uint32_t wt = in ? w[e] : 0u;
+            const int32_t c = in ? col[e] : 0;
+            const bool light = in && wt < delta;
+            const bool hv = in && !light;
+            const unsigned long long ml = __ballot(light), mh = __ballot(hv);
+            if (light) {
+                const int32_t k = lo + static_cast<int32_t>(lane_rank(ml));
+                scol[k] = c;
+                sw[k] = wt;
+            }
+            if (hv) {
+                const int32_t k = hi + static_cast<int32_t>(lane_rank(mh));
+                scol[k] = c;
+                sw[k] = wt;
+            }
+            lo += __popcll(ml);
+            hi += __popcll(mh);
+        }
+        if (lane == 0) {
+            split[u] = r0 + nl;
+            heavy += static_cast<unsigned long long>(r1 - r0 - nl);
+        }
+    }
+    if (lane == 0 && heavy) atomicAdd(heavy_total, heavy);
+}
+
+// (Re)build the partition of g's SSSP copy at `delta` (synchronous).
+irgl_status build_partition(irgl_graph_s *g, uint32_t delta) {
+    g->split = nullptr;
+    g->split_delta = IRGL_DELTA_NONE;
+    if (!g->scol || delta == IRGL_DELTA_NONE || g->m == 0) return IRGL_OK;
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, 0);
+    IRGL_HIP(hipGetLastError());
+    unsigned long long *heavy = nullptr;
+    IRGL_HIP(hipGetSymbolAddress(reinterpret_cast<void **>(&heavy), HIP_SYMBOL(g_heavy_edges)));
+    const int egrid = std::max(1, std::min(4096, (g->n + 3) / 4));  // 4 wavefronts per workgroup
+    hipLaunchKernelGGL(partition_rows_kernel, dim3(egrid), dim3(256), 0, 0, g->n, g->row_ptr, g->col, g->w,
+                       delta, g->scol, g->sw, g->split_store, heavy);
+    IRGL_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    IRGL_HIP(hipMemcpy(&h, heavy, 8, hipMemcpyDeviceToHost));
+    g->split = h ? g->split_store : nullptr;
+    g->split_delta = delta;
+    return IRGL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -837,7 +964,7 @@ __global__ void relabel_edges_kernel(int32_t n, const int32_t *perm, const int32
 // Store of a relabelled copy: row offsets, targets, weights, perm, then the
 // build's scratch (sort keys, ids, inverse, library sort/scan scratch).
 struct ReorderLayout {
-    size_t nrp, ncol, nw, perm, keys_in, keys_out, ids_in, inv, tmp, tmp_bytes, total;
+    size_t nrp, ncol, nw, scol, sw, split, perm, keys_in, keys_out, ids_in, inv, tmp, tmp_bytes, total;
 };
 
 irgl_status reorder_layout(int32_t n, int64_t m, bool weighted, ReorderLayout *out) {
@@ -846,7 +973,11 @@ irgl_status reorder_layout(int32_t n, int64_t m, bool weighted, ReorderLayout *o
     L.nrp = 0;
     L.ncol = align_up(static_cast<size_t>(n + 1) * 4);
     L.nw = L.ncol + align_up(static_cast<size_t>(m) * 4 + 4);
-    L.perm = L.nw + (weighted ? align_up(static_cast<size_t>(m) * 4 + 4) : 0);
+    // weighted: the SSSP copy (partitioned targets and weights, split points)
+    L.scol = L.nw + (weighted ? align_up(static_cast<size_t>(m) * 4 + 4) : 0);
+    L.sw = L.scol + (weighted ? align_up(static_cast<size_t>(m) * 4 + 4) : 0);
+    L.split = L.sw + (weighted ? align_up(static_cast<size_t>(m) * 4 + 4) : 0);
+    L.perm = L.split + (weighted ? nb : 0);
     L.keys_in = L.perm + nb;
     L.keys_out = L.keys_in + nb;
     L.ids_in = L.keys_out + nb;
@@ -992,6 +1123,8 @@ irgl_status irgl_graph_upload(const irgl_csr *csr, irgl_graph *out) {
     g->orig_col = csr->col;
     g->orig_w = csr->w;
     g->perm = nullptr;
+    g->inv = nullptr;
+    g->qdelta = delta_rule(g, false);
     *out = g;
     return IRGL_OK;
 }
@@ -1063,8 +1196,37 @@ irgl_status irgl_graph_upload_reordered(const irgl_csr *csr, void *store, size_t
     g->orig_col = csr->col;
     g->orig_w = csr->w;
     g->perm = perm;
+    g->inv = inv;
+    if (nw) {
+        g->scol = reinterpret_cast<int32_t *>(b + L.scol);
+        g->sw = reinterpret_cast<uint32_t *>(b + L.sw);
+        g->split_store = reinterpret_cast<int32_t *>(b + L.split);
+        g->qdelta = delta_rule(g, true);
+        st = build_partition(g, g->qdelta);
+        if (st) {
+            delete g;
+            return st;
+        }
+    } else {
+        g->qdelta = delta_rule(g, false);
+    }
     *out = g;
     return IRGL_OK;
+}
+
+irgl_status irgl_graph_set_delta(irgl_graph g, uint32_t delta) {
+    if (!g || delta == 0) return IRGL_ERR_INVALID_ARGUMENT;
+    if (!g->scol) {  // no SSSP copy: only the default step changes
+        g->qdelta = delta;
+        return IRGL_OK;
+    }
+    int cur = -1;
+    IRGL_HIP(hipGetDevice(&cur));
+    if (cur != g->device) IRGL_HIP(hipSetDevice(g->device));
+    const irgl_status st = build_partition(g, delta);
+    if (st == IRGL_OK) g->qdelta = delta;
+    if (cur != g->device) (void)hipSetDevice(cur);
+    return st;
 }
 
 irgl_status irgl_graph_free(irgl_graph g) {
@@ -1129,18 +1291,32 @@ irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out) {
 
 irgl_status irgl_control_block_sizes(int32_t *sizes, int32_t cap, int32_t *count) {
     if (!count || (cap > 0 && !sizes)) return IRGL_ERR_INVALID_ARGUMENT;
-    // T_BFS and T_SSSP: the fixed workgroup sizes each loop body is compiled
-    // for; the batched control kernel holds both bodies, so T_control is
-    // their intersection.
-    const int32_t t_bfs[] = {256, 512, 1024};
-    const int32_t t_sssp[] = {256, 512, 1024};
+    // T_BFS and T_SSSP from the bodies' own constraints: both are
+    // ElasticBlock loop bodies whose nested edge scheduler keeps a per-thread
+    // gather window and per-wavefront push queues in LDS (Smem<B>, linear in
+    // the workgroup size); the batched control kernel holds both, so its sizes
+    // are those (among the sizes it is compiled for) that both admit within
+    // the device's per-workgroup LDS.
+    const long long l64 = static_cast<long long>(sizeof(Smem<64>));
+    const long long l1024 = static_cast<long long>(sizeof(Smem<1024>));
+    const int32_t per = static_cast<int32_t>((l1024 - l64 + 959) / 960);
+    const int32_t base = static_cast<int32_t>(std::max(0ll, l64 - 64ll * per));
+    const irgl_block_constraint body = {IRGL_BLOCK_ELASTIC, 1024, base, per};
+    int lds = 0, dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 && hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipGetLastError();
+    if (lds <= 0) lds = 65536;  // no device: gfx950's per-workgroup LDS limit
+    const int32_t compiled[] = {256, 512, 1024};  // batch_kernel<B> instantiations
     int32_t k = 0;
-    for (int32_t a : t_bfs)
-        for (int32_t b : t_sssp)
-            if (a == b) {
-                if (k < cap) sizes[k] = a;
-                ++k;
-            }
+    for (int32_t b : compiled) {
+        const irgl_block_constraint ks[3] = {body, body, {IRGL_BLOCK_FIXED, b, 0, 0}};
+        int32_t chosen = 0;
+        if (irgl_control_block(ks, 3, lds, &chosen) == IRGL_OK) {
+            if (k < cap) sizes[k] = b;
+            ++k;
+        }
+    }
     *count = k;
     return IRGL_OK;
 }
@@ -1374,6 +1550,7 @@ irgl_status irgl_batch_open(const irgl_graph *graphs, int32_t ngraphs, const irg
     sp->gang.off_far0 = P.G.off_far0;
     sp->gang.off_far1 = P.G.off_far1;
     sp->gang.off_far_flag = P.G.off_far_flag;
+    sp->gang.off_expd = P.G.off_expd;
     sp->gang.off_visited = P.G.off_visited;
     sp->gang.off_hub_v = P.G.off_hub_v;
     sp->gang.off_hub_base = P.G.off_hub_base;

@@ -42,7 +42,7 @@ struct BatchParams {
     unsigned long long team_bytes;
     // offsets inside one team's scratch
     unsigned long long off_wl0, off_wl1, off_stamp, off_shadow, off_far0, off_far1, off_far_flag, off_visited,
-        off_hub_v, off_hub_base;
+        off_hub_v, off_hub_base, off_expd;
     uint32_t cap;              // worklist capacity = largest n
     uint32_t hub_cap;
     int32_t team;              // workgroups per team
@@ -69,6 +69,14 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.far1 = sssp ? reinterpret_cast<int32_t *>(base + bp.off_far1) : nullptr;
     p.far_flag = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_far_flag) : nullptr;
     p.far_cap = static_cast<uint32_t>(t.n);
+    p.expd = sssp ? reinterpret_cast<uint32_t *>(base + bp.off_expd) : nullptr;
+    p.split = nullptr;  // batched tasks run on the caller's rows (no light/heavy partition)
+    p.hlist = nullptr;
+    p.hstamp = nullptr;
+    p.hcap = 0;
+    p.inv = nullptr;  // results are written under the caller's ids directly
+    p.out_caller = nullptr;
+    p.parent_caller = nullptr;
     // SSSP without refreshes would only test a bitmap holding the source
     p.visited = (sssp && t.t_bitmap == kInf) ? nullptr : reinterpret_cast<uint32_t *>(base + bp.off_visited);
     p.t_bitmap = t.t_bitmap;

@@ -70,7 +70,9 @@ struct alignas(128) Ctrl {
     int32_t grid;
     int32_t block;
     unsigned long long fedges;  // sum of out-degrees of every frontier
-    uint32_t pad4[22];
+    // rotating SSSP heavy-list counters (indexed by threshold raises so far)
+    uint32_t hcnt[3];
+    uint32_t pad4[19];
 };
 static_assert(sizeof(Ctrl) == 13 * 128, "control block layout");
 

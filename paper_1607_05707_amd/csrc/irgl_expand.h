@@ -17,7 +17,7 @@ struct Sink {
     uint32_t *min_out;  // far list: running lower bound of listed distances
 };
 
-// The wavefront's two staging queues and where they drain to.
+// The wavefront's staging queues and where they drain to.
 struct Pushers {
     WaveQueue<kQueueCap> nq;  // outgoing worklist (near)
     WaveQueue<kQueueCap> fq;  // SSSP far list
@@ -29,13 +29,62 @@ struct Pushers {
     unsigned long long mf;    // this lane's sum of out-degrees of pushed vertices
     uint32_t tries = 0;       // this lane's claim atomics (trace statistics)
     uint32_t wins = 0;        // ... and the successful ones
+    WaveQueue<kHeavyQ> hq{nullptr, 0};  // SSSP heavy list of the current bucket
+    Sink skh{};               // its sink (cnt_out null: no heavy list in this invocation)
     __device__ __forceinline__ void near(bool p, int item) {
         nq.push(p, item, sk.cnt_out, sk.out, sk.cap, sk.ctrl);
     }
     __device__ __forceinline__ void far(bool p, int item) {
         fq.push(p, item, skf.cnt_out, skf.out, skf.cap, skf.ctrl);
     }
+    // All 64 lanes call it (uniform call site); does nothing without a list.
+    __device__ __forceinline__ void heavy(bool p, int item) {
+        if (skh.cnt_out) hq.push(p, item, skh.cnt_out, skh.out, skh.cap, skh.ctrl);
+    }
 };
+
+// Row range an operator relaxes for vertex v (default: the whole row).
+template <class Op>
+__device__ __forceinline__ void op_range(const Op &, const int32_t *__restrict__ rp, int v, int &r0, int &r1) {
+    r0 = rp[v];
+    r1 = rp[v + 1];
+}
+template <>
+__device__ __forceinline__ void op_range<SsspOp>(const SsspOp &op, const int32_t *__restrict__ rp, int v, int &r0,
+                                                 int &r1) {
+    if (!op.split) {
+        r0 = rp[v];
+        r1 = rp[v + 1];
+    } else if (op.heavy) {
+        r0 = op.split[v];
+        r1 = rp[v + 1];
+    } else {
+        r0 = rp[v];
+        r1 = op.split[v];
+    }
+}
+
+// Pop-time decision for vertex v with value val (default: expand it).
+// SSSP: a vertex whose distance has not changed since its last expansion is
+// not expanded again (every edge was relaxed with this distance, or a
+// smaller one no longer current is impossible: distances only fall); an
+// expanded vertex is listed once per bucket for the heavy pass (*hpush).
+template <class Op>
+__device__ __forceinline__ bool op_pop(const Op &, int, uint32_t, bool &) {
+    return true;
+}
+template <>
+__device__ __forceinline__ bool op_pop<SsspOp>(const SsspOp &op, int v, uint32_t val, bool &hpush) {
+    if (op.expd) {
+        if (op.expd[v] == val) return false;
+        op.expd[v] = val;
+    }
+    if (op.hstamp && op.hstamp[v] != op.bucket) {
+        op.hstamp[v] = op.bucket;
+        hpush = true;
+    }
+    return true;
+}
 
 // Workgroup-wide drain of both queues (all threads call it).
 template <int B, class Op, class S>
@@ -49,6 +98,8 @@ __device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
         if (lane_id() == 0 && x) atomicAdd(pu.mf_out, x);
         pu.mf = 0;
     }
+    if (Op::kFar && pu.skh.cnt_out)  // uniform: the same sink for the whole team
+        block_drain<B, kHeavyQ>(pu.hq, sm.fill, &sm.base, pu.skh.cnt_out, pu.skh.out, pu.skh.cap, pu.skh.ctrl);
     if (Op::kFar) {
         block_drain<B, kQueueCap>(pu.fq, sm.fill, &sm.base, pu.skf.cnt_out, pu.skf.out, pu.skf.cap,
                                   pu.skf.ctrl);
@@ -162,10 +213,9 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             return;
         }
         val = op.vertex_value(v);
-        if (op.active(val)) {
-            r0 = row_ptr[v];
-            r1 = row_ptr[v + 1];
-        }
+        bool hp = false;
+        if (op.active(val) && op_pop(op, v, val, hp)) op_range(op, row_ptr, v, r0, r1);
+        pu.heavy(hp && lane == 0, v);
         const int deg = r1 - r0;
         if (lane == 0) edges += static_cast<unsigned long long>(deg);
         if (deg >= B) {  // a range of a whole round or more goes to the grid tier
@@ -199,6 +249,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         const uint32_t i = base + tid;
         int v = -1, r0 = 0, r1 = 0;
         uint32_t val = 0;
+        bool hp = false;
         if (i < cnt_in) {
             v = in ? in[i] : static_cast<int>(i);
             if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
@@ -206,12 +257,10 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                 v = -1;
             } else {
                 val = op.vertex_value(v);
-                if (op.active(val)) {
-                    r0 = row_ptr[v];
-                    r1 = row_ptr[v + 1];
-                }
+                if (op.active(val) && op_pop(op, v, val, hp)) op_range(op, row_ptr, v, r0, r1);
             }
         }
+        pu.heavy(hp, v);
         int deg = r1 - r0;
         edges += static_cast<unsigned long long>(deg);
 
@@ -347,7 +396,8 @@ __device__ __forceinline__ void expand_hubs(uint32_t nhubs, uint32_t nchunks, co
     while (c < hi && h < nhubs) {
         const int v = hub_v[h];
         const uint32_t cb = hub_base[h];
-        const int r0 = row_ptr[v], r1 = row_ptr[v + 1];
+        int r0, r1;
+        op_range(op, row_ptr, v, r0, r1);
         const uint32_t nch = static_cast<uint32_t>((r1 - r0 + kChunk - 1) / kChunk);
         const uint32_t c_end = min(hi, cb + nch);
         const int e_lo = r0 + static_cast<int>((c - cb) * kChunk);
@@ -365,10 +415,13 @@ __device__ __forceinline__ void expand_hubs(uint32_t nhubs, uint32_t nchunks, co
 // distance by a near invocation (dropped); one below t_new joins the next
 // worklist; the rest stays listed.  Called by all threads of every workgroup.
 // ---------------------------------------------------------------------------
+// A vertex moved to the worklist claims its push stamp for invocation `it`,
+// so that a relaxation in the same invocation cannot list it a second time.
 template <int B>
 __device__ __forceinline__ void far_transfer(const int32_t *far_in, uint32_t far_n, uint32_t n,
                                              uint32_t t_old, uint32_t t_new, const uint32_t *dist,
-                                             uint32_t *far_flag, Pushers &pu, Team tm) {
+                                             uint32_t *far_flag, uint32_t *stamp, uint32_t it, Pushers &pu,
+                                             Team tm) {
     const uint32_t stride = tm.size * B;
     for (uint32_t base = tm.id * B; base < far_n; base += stride) {
         const uint32_t i = base + threadIdx.x;
@@ -383,6 +436,7 @@ __device__ __forceinline__ void far_transfer(const int32_t *far_in, uint32_t far
                 const uint32_t dv = dist[v];
                 if (dv < t_new) far_flag[v] = 0u;
                 to_near = dv >= t_old && dv < t_new;
+                if (to_near) to_near = atomicExch(&stamp[v], it) != it;
                 keep = dv >= t_new;
                 if (keep) pu.fmin = min(pu.fmin, dv);
             }

@@ -8,6 +8,7 @@ namespace irgl {
 
 
 constexpr int kQueueCap = 256;  // LDS staging entries per wavefront
+constexpr int kHeavyQ = 64;     // LDS staging entries per wavefront for the SSSP heavy list
 constexpr int kUMax = 4;        // largest edges-per-lane-per-round of any operator
 
 // Shared-memory layout of the frontier kernels for workgroup size B.
@@ -22,6 +23,7 @@ struct Smem {
     int fill[NW];                  // per-wavefront queue fill at the workgroup drain
     int queue[NW][kQueueCap];      // worklist (near) staging
     int queue_far[NW][kQueueCap];  // SSSP far-list staging
+    int queue_heavy[NW][kHeavyQ];  // SSSP heavy-list staging (vertices expanded in the current bucket)
     int owner;                     // workgroup-tier vertex owner
     int big_r0, big_r1, big_v;
     uint32_t big_val;
@@ -77,6 +79,18 @@ struct Params {
     uint32_t do_beta;
     long long m;          // edges of the graph
     uint32_t reduce_all;  // topology-driven loop: 1 = Iterate Until All(unchanged), 0 = While Any(changed)
+    // SSSP light/heavy split (rows partitioned at upload: edges lighter than
+    // `delta` first): split[v] = first heavy edge of v, or null (no split)
+    const int32_t *split;
+    uint32_t *expd;       // SSSP: distance of each vertex's last expansion (INF: never), or null
+    int32_t *hlist;       // SSSP split: vertices expanded in the current bucket
+    uint32_t *hstamp;     // ... and the bucket in which each was last listed
+    uint32_t hcap;
+    // relabelled graph, outlined loop: map the results to caller ids at the
+    // end of the launch (out_caller[o] = val[inv[o]]), or null
+    const int32_t *inv;
+    uint32_t *out_caller;
+    int32_t *parent_caller;
 };
 
 // ---------------------------------------------------------------------------
@@ -160,6 +174,18 @@ struct SsspOp {
     // its lines stay cacheable in L2 while dist's lines, hammered by atomics,
     // do not.  A relaxation that cannot beat the bound cannot improve dist.
     uint32_t *shadow;
+    // Light/heavy split (null: every edge is relaxed when its source is
+    // expanded).  Rows are partitioned so that edges lighter than the step
+    // come first; an expansion relaxes only [row_ptr[v], split[v]) and lists
+    // v for the bucket's heavy pass, which relaxes [split[v], row_ptr[v+1])
+    // once, with v's final distance, after the bucket has drained.
+    const int32_t *split = nullptr;
+    // distance of each vertex's last expansion: a popped vertex whose
+    // distance equals it has already relaxed its edges with that distance
+    uint32_t *expd = nullptr;
+    uint32_t *hstamp = nullptr;  // bucket of each vertex's last heavy-list entry
+    uint32_t bucket = 0;         // current bucket (threshold raises so far)
+    uint32_t heavy = 0;          // 1: this invocation relaxes heavy ranges
     __device__ __forceinline__ uint32_t vertex_value(int v) const { return dist[v]; }
     __device__ __forceinline__ bool active(uint32_t) const { return true; }
     __device__ __forceinline__ void relax(const int (&e)[kU], const int (&d)[kU], const int (&)[kU],

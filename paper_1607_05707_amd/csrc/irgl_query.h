@@ -24,6 +24,8 @@ __device__ __forceinline__ void init_arrays(const Params &p, int with_stamp, Tea
             p.stamp[i] = kInf;
             p.shadow[i] = s ? 0u : kInf;
             p.far_flag[i] = 0u;
+            if (p.expd) p.expd[i] = kInf;
+            if (p.hstamp) p.hstamp[i] = kInf;
         }
         if (p.visited && (i & 31u) == 0u)
             p.visited[i >> 5] = (static_cast<uint32_t>(p.src) >> 5 == i >> 5)
@@ -45,6 +47,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
             c->hub[k] = 0;
             c->far_cnt[k] = 0;
             c->far_min[k] = kInf;
+            c->hcnt[k] = 0;
         }
         if (reset_barrier) reset_barrier_words(c);
         c->error = 0;
@@ -67,16 +70,27 @@ __global__ void init_kernel(Params p, int with_stamp) {
     if (blockIdx.x == 0 && threadIdx.x == 0) init_control(p, true);
 }
 
+// The operator of invocation `it`.  SSSP: `bucket` is the number of
+// threshold raises so far; `heavy` selects the heavy pass of a split graph
+// (heavy ranges, no pop-time skip or listing).
 template <class Op>
-__device__ __forceinline__ Op make_op(const Params &p, uint32_t it, uint32_t thresh);
+__device__ __forceinline__ Op make_op(const Params &p, uint32_t it, uint32_t thresh, uint32_t bucket = 0,
+                                      bool heavy = false);
 
 template <>
-__device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh) {
-    return SsspOp{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited, p.shadow};
+__device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh, uint32_t bucket,
+                                                  bool heavy) {
+    SsspOp op{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited, p.shadow};
+    op.split = p.split;
+    op.expd = heavy ? nullptr : p.expd;
+    op.hstamp = (heavy || !p.split) ? nullptr : p.hstamp;
+    op.bucket = bucket;
+    op.heavy = heavy ? 1u : 0u;
+    return op;
 }
 
 template <>
-__device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it, uint32_t) {
+__device__ __forceinline__ BfsOp make_op<BfsOp>(const Params &p, uint32_t it, uint32_t, uint32_t, bool) {
     return BfsOp{p.val, p.parent, p.visited, it + 1, p.perm};
 }
 
@@ -338,6 +352,11 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     const int wid = tid / kWave;
     Ctrl *ctrl = p.ctrl;
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, {}, {}, kInf};
+    pu.hq.q = sm.queue_heavy[wid];
+    // SSSP light/heavy split: expansions relax light ranges and list the
+    // vertex for its bucket's heavy pass, which runs in the bucket's transfer
+    // invocation (one barrier for both)
+    const bool split = Op::kFar && p.split != nullptr;
     LoopResult r{0u, 0ull, 0ull, 0u, 0ull};
     // BFS direction choice (needs the frontier bitmap; symmetric graphs only)
     bool can_pull = !Op::kFar && p.frontier != nullptr;
@@ -361,11 +380,12 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     for (;; ++it) {
         uint32_t cnt_in = load_agent(&ctrl->cnt[it % 3]);
         if (cnt_in > p.cap) cnt_in = p.cap;  // overflowed pushes were dropped (error set)
-        uint32_t far_n = 0;
+        uint32_t far_n = 0, nheavy = 0;
         if (cnt_in == 0) {
             if (!Op::kFar) break;
             far_n = min(load_agent(&ctrl->far_cnt[tr % 3]), p.far_cap);
-            if (far_n == 0) break;
+            if (split) nheavy = min(load_agent(&ctrl->hcnt[tr % 3]), p.hcap);
+            if (far_n == 0 && nheavy == 0) break;
         }
         if (it >= p.max_iter) {
             if (lead) set_error(ctrl, kErrIterLimit, false);
@@ -381,23 +401,50 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             if (cnt_in == 0) {
                 store_agent(&ctrl->far_cnt[(tr + 2) % 3], 0u);
                 store_agent(&ctrl->far_min[(tr + 2) % 3], kInf);
+                store_agent(&ctrl->hcnt[(tr + 1) % 3], 0u);  // the next bucket's heavy list
             }
             if (tracing(p, it)) trace_start(p, it, cnt_in);
         }
         pu.sk = Sink{&ctrl->cnt[(it + 1) % 3], out, p.cap, ctrl};
         unsigned long long *hub_ctr = &ctrl->hub[it % 3];
         if (cnt_in == 0) {
-            // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1
-            const uint32_t t_new = next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta);
+            // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1.
+            // With an empty far list (only a heavy pass left) the threshold
+            // rises by one step, so the heavy results keep their bucket order.
+            const uint32_t t_new =
+                far_n ? next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta)
+                      : raise_threshold(thresh, p.delta);
             if (p.visited && r.items - refreshed >= p.t_bitmap) {
                 refresh_bitmap(p, tm, thresh);  // every distance below thresh is final
                 refreshed = r.items;
             }
             pu.skf = far_sink(p, tr + 1);
+            pu.skh = Sink{};
             far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), thresh, t_new,
-                            p.val, p.far_flag, pu, tm);
+                            p.val, p.far_flag, p.stamp, it, pu, tm);
+            // heavy pass of the drained bucket (split graphs): its vertices'
+            // distances are final, so each heavy edge is relaxed once; the
+            // results (at least thresh) go to the next worklist (below t_new)
+            // or the far list
+            const unsigned long long edges_before = r.edges;
+            const Op hop = make_op<Op>(p, it, t_new, tr, true);
+            if (nheavy > 0)
+                expand<B, Op>(p.hlist, nheavy, static_cast<uint32_t>(p.n), p.row_ptr, p.col, hop, sm, pu, p.t_wave,
+                              p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm,
+                              &ctrl->tile[it % 3]);
             drain_all<B, Op>(pu, sm);
             if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            if (nheavy > 0 && p.t_grid > 0) {
+                uint32_t nh, nchunks;
+                hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
+                           nh, nchunks);
+                if (nh > 0) {
+                    expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, hop, sm, pu, tm);
+                    drain_all<B, Op>(pu, sm);
+                    if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+                }
+            }
+            if (nheavy > 0 && tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
             thresh = t_new;
             ++tr;
         } else if (can_pull && ([&] {
@@ -442,13 +489,14 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
         } else {
             bitmaps_current = false;  // top-down labels are not in the bitmaps
             pu.skf = far_sink(p, tr);
+            pu.skh = split ? Sink{&ctrl->hcnt[tr % 3], p.hlist, p.hcap, ctrl, nullptr} : Sink{};
             pu.mf_out = &ctrl->mf[(it + 1) % 3];
             const unsigned long long edges_before = r.edges;
             if (!Op::kFar && p.visited && r.items - refreshed >= p.t_bitmap) {
                 refresh_bitmap(p, tm, kInf);  // BFS: visited = labelled
                 refreshed = r.items;
             }
-            const Op op = make_op<Op>(p, it, thresh);
+            const Op op = make_op<Op>(p, it, thresh, tr, false);
             const bool tr_on = tracing(p, it);
             unsigned long long busy_a = tr_on ? wall_clock64() : 0ull, busy_b = 0;
             expand<B, Op>(in, cnt_in, static_cast<uint32_t>(p.n), p.row_ptr, p.col, op, sm, pu, p.t_wave,
@@ -506,6 +554,18 @@ __device__ __forceinline__ void finish_query(const Params &p, const LoopResult &
     }
 }
 
+// Results of a relabelled graph under caller ids: a gather over caller ids
+// (coalesced reads of inv and coalesced writes, one random read of the
+// internal-id values each), by the whole team after its last barrier.
+__device__ __forceinline__ void map_to_caller(const Params &p, Team tm) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    for (uint32_t o = tm.id * blockDim.x + threadIdx.x; o < n; o += tm.size * blockDim.x) {
+        const int32_t v = p.inv[o];
+        p.out_caller[o] = p.val[v];
+        if (p.parent_caller) p.parent_caller[o] = p.parent[v];
+    }
+}
+
 // One query per cooperative launch: the whole grid is the team.
 template <int B, class Op>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(Op::kMinWaves))) void persistent_kernel(
@@ -514,6 +574,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(Op::kMinWaves
     const Team tm = whole_grid();
     BarrierState bs = make_barrier_state(p.wd_ticks, p.barrier);
     const LoopResult r = run_iterate<B, Op>(p, sm, tm, bs);
+    // every value is final: the loop ended after a barrier that followed the
+    // last write of any workgroup
+    if (p.inv) map_to_caller(p, tm);
     finish_query<B>(p, r, tm);
 }
 
@@ -594,7 +657,7 @@ __global__ __launch_bounds__(B) void transfer_kernel(Params p, uint32_t far_n, u
     }
     if (p.refresh && p.visited) refresh_bitmap(p, whole_grid(), p.thresh);
     far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), p.thresh, t_new, p.val,
-                    p.far_flag, pu, whole_grid());
+                    p.far_flag, p.stamp, it, pu, whole_grid());
     drain_all<B, SsspOp>(pu, sm);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctrl->cnt[(it + 2) % 3] = 0;

@@ -138,6 +138,8 @@ _lib.irgl_graph_free.restype = ctypes.c_int32
 _lib.irgl_graph_free.argtypes = [_c]
 _lib.irgl_graph_default_delta.restype = ctypes.c_int32
 _lib.irgl_graph_default_delta.argtypes = [_c, ctypes.POINTER(ctypes.c_uint32)]
+_lib.irgl_graph_set_delta.restype = ctypes.c_int32
+_lib.irgl_graph_set_delta.argtypes = [_c, ctypes.c_uint32]
 _lib.irgl_workspace_bytes.restype = ctypes.c_int32
 _lib.irgl_workspace_bytes.argtypes = [_c, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(irgl_config),
                                       ctypes.POINTER(ctypes.c_size_t)]
@@ -446,6 +448,12 @@ def read_stats(buf: torch.Tensor) -> dict:
     return st.as_dict()
 
 
+def read_stats_array(buf: torch.Tensor) -> list:
+    """Decode a device [k, STATS_BYTES] array of irgl_stats (one copy)."""
+    raw = buf.cpu().numpy()
+    return [irgl_stats.from_buffer_copy(bytes(raw[i].tobytes())).as_dict() for i in range(raw.shape[0])]
+
+
 def as_u32_numpy(t: torch.Tensor):
     """Device int32 tensor holding uint32 bits -> host numpy uint32."""
     return t.cpu().numpy().view("uint32")
@@ -478,6 +486,12 @@ def irgl_graph_default_delta(g: Graph) -> int:
     out = ctypes.c_uint32()
     _check(_lib.irgl_graph_default_delta(g.handle, ctypes.byref(out)), "irgl_graph_default_delta")
     return int(out.value)
+
+
+def irgl_graph_set_delta(g: Graph, delta: int) -> None:
+    """Set the default SSSP step of single queries on g (rebuilds the
+    light/heavy partition of a relabelled weighted graph; synchronous)."""
+    _check(_lib.irgl_graph_set_delta(g.handle, int(delta)), "irgl_graph_set_delta")
 
 
 def upload(g, flags: int = IRGL_VALIDATE, reorder: bool = False) -> Graph:
@@ -744,3 +758,150 @@ def irgl_batch_launches(s: Server):
 
 def irgl_batch_close(s: Server) -> None:
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Pipes (irgl_pipe_*): orchestration programs run by one outlined control
+# kernel over the shared in / out / retry worklists.
+# ---------------------------------------------------------------------------
+
+IRGL_PIPE_INVOKE, IRGL_PIPE_ITERATE, IRGL_PIPE_BEGIN, IRGL_PIPE_END = 0, 1, 2, 3
+IRGL_PIPE_IF, IRGL_PIPE_JUMP, IRGL_PIPE_INIT_SOURCE = 4, 5, 6
+IRGL_COND_IN_EMPTY, IRGL_COND_FRONTIER_LARGE, IRGL_COND_RETURNED = 0, 1, 2
+IRGL_COND_NOT = 0x100
+(IRGL_BODY_BFS_PUSH, IRGL_BODY_BFS_PULL, IRGL_BODY_MST_INIT, IRGL_BODY_MST_FINDMIN, IRGL_BODY_MST_HOOK,
+ IRGL_BODY_MST_JUMP, IRGL_BODY_MST_RELABEL, IRGL_BODY_MST_MINID, IRGL_BODY_MST_LABEL) = range(9)
+IRGL_BODY_COUNT = 9
+IRGL_BLOCK_ELASTIC, IRGL_BLOCK_SHRINKABLE, IRGL_BLOCK_FIXED = 0, 1, 2
+
+
+class irgl_block_constraint(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("block", ctypes.c_int32), ("lds_base", ctypes.c_int32),
+                ("lds_per_thread", ctypes.c_int32)]
+
+
+class irgl_pipe_op(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class irgl_pipe_io(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("level", ctypes.c_void_p), ("component", ctypes.c_void_p),
+                ("in_forest", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("trace", ctypes.c_void_p),
+                ("trace_len", ctypes.c_uint32), ("block", ctypes.c_int32), ("max_invocations", ctypes.c_uint32),
+                ("watchdog_ms", ctypes.c_uint32), ("grid", ctypes.c_int32), ("force_retry", ctypes.c_uint32)]
+
+
+_lib.irgl_control_block.restype = ctypes.c_int32
+_lib.irgl_control_block.argtypes = [ctypes.POINTER(irgl_block_constraint), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32)]
+_lib.irgl_pipe_body_constraint.restype = ctypes.c_int32
+_lib.irgl_pipe_body_constraint.argtypes = [ctypes.c_int32, ctypes.POINTER(irgl_block_constraint)]
+_lib.irgl_pipe_check.restype = ctypes.c_int32
+_lib.irgl_pipe_check.argtypes = [ctypes.POINTER(irgl_pipe_op), ctypes.c_int32]
+_lib.irgl_pipe_control_block.restype = ctypes.c_int32
+_lib.irgl_pipe_control_block.argtypes = [ctypes.POINTER(irgl_pipe_op), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+_lib.irgl_pipe_workspace_bytes.restype = ctypes.c_int32
+_lib.irgl_pipe_workspace_bytes.argtypes = [_c, ctypes.POINTER(irgl_pipe_op), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_pipe_run.restype = ctypes.c_int32
+_lib.irgl_pipe_run.argtypes = [_c, ctypes.POINTER(irgl_pipe_op), ctypes.c_int32, ctypes.POINTER(irgl_pipe_io), _c,
+                               ctypes.c_size_t, _c, _c]
+
+
+def _program(ops):
+    arr = (irgl_pipe_op * len(ops))()
+    for i, o in enumerate(ops):
+        o = tuple(o) + (0,) * (3 - len(o))
+        arr[i].op, arr[i].a, arr[i].b = int(o[0]), int(o[1]), int(o[2])
+    return arr
+
+
+def irgl_control_block(constraints, lds_limit: int) -> int:
+    """T_control of (kind, block, lds_base, lds_per_thread) tuples; raises on an empty set."""
+    arr = (irgl_block_constraint * max(1, len(constraints)))()
+    for i, c in enumerate(constraints):
+        arr[i].kind, arr[i].block, arr[i].lds_base, arr[i].lds_per_thread = (int(x) for x in c)
+    out = ctypes.c_int32()
+    _check(_lib.irgl_control_block(arr, len(constraints), int(lds_limit), ctypes.byref(out)), "irgl_control_block")
+    return int(out.value)
+
+
+def irgl_pipe_body_constraint(body: int):
+    c = irgl_block_constraint()
+    _check(_lib.irgl_pipe_body_constraint(int(body), ctypes.byref(c)), "irgl_pipe_body_constraint")
+    return (c.kind, c.block, c.lds_base, c.lds_per_thread)
+
+
+def irgl_pipe_check(ops) -> None:
+    arr = _program(ops)
+    _check(_lib.irgl_pipe_check(arr, len(ops)), "irgl_pipe_check")
+
+
+def irgl_pipe_control_block(ops, requested: int = 0, lds_limit: int = 0) -> int:
+    arr = _program(ops)
+    out = ctypes.c_int32()
+    _check(_lib.irgl_pipe_control_block(arr, len(ops), int(requested), int(lds_limit), ctypes.byref(out)),
+           "irgl_pipe_control_block")
+    return int(out.value)
+
+
+def irgl_pipe_workspace_bytes(g: Graph, ops) -> int:
+    arr = _program(ops)
+    out = ctypes.c_size_t()
+    _check(_lib.irgl_pipe_workspace_bytes(g.handle, arr, len(ops), ctypes.byref(out)), "irgl_pipe_workspace_bytes")
+    return int(out.value)
+
+
+def irgl_pipe_run(g: Graph, ops, src: int = 0, level=None, component=None, in_forest=None, weight=None,
+                  trace=None, block: int = 0, max_invocations: int = 0, grid: int = 0, ws=None, stream=None,
+                  stats=None, force_retry: bool = False):
+    """Run a pipe program on g (asynchronous on `stream`)."""
+    arr = _program(ops)
+    if ws is None:
+        ws = torch.empty(irgl_pipe_workspace_bytes(g, ops), dtype=torch.uint8, device=g.row_ptr.device)
+    io = irgl_pipe_io()
+    io.src = int(src)
+    io.level = _dev_ptr(level, "level", _I32, g.n)
+    io.component = _dev_ptr(component, "component", _I32, g.n)
+    io.in_forest = _dev_ptr(in_forest, "in_forest", (torch.uint8,), g.m) if in_forest is not None else None
+    io.weight = _dev_ptr(weight, "weight", (torch.int64,), 1)
+    io.trace = _dev_ptr(trace, "trace", _I32)
+    io.trace_len = int(trace.numel()) if trace is not None else 0
+    io.block = int(block)
+    io.max_invocations = int(max_invocations)
+    io.grid = int(grid)
+    io.force_retry = 1 if force_retry else 0
+    sp = _dev_ptr(stats, "stats", (torch.uint8,), STATS_BYTES) if stats is not None else None
+    _check(_lib.irgl_pipe_run(g.handle, arr, len(ops), ctypes.byref(io), _dev_ptr(ws, "ws", (torch.uint8,)),
+                              ws.numel(), _stream_handle(stream), sp), "irgl_pipe_run")
+    return ws
+
+
+def pipe_bfs_program():
+    """BFS whose every level is consumed by the top-down or the bottom-up body,
+    chosen at run time by the size of the frontier (dynamic piping)."""
+    return [(IRGL_PIPE_INIT_SOURCE,),
+            (IRGL_PIPE_BEGIN, 0),
+            (IRGL_PIPE_IF, IRGL_COND_FRONTIER_LARGE, 5),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_BFS_PULL),
+            (IRGL_PIPE_JUMP, 6),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_BFS_PUSH),
+            (IRGL_PIPE_END,)]
+
+
+def pipe_boruvka_program():
+    """Boruvka minimum spanning forest as a Pipe Once around a looping Pipe:
+    find-min-edge (non-blocking Atomic, Else -> retry), hook, Iterate pointer
+    jumping, relabel; then the smallest id of every tree."""
+    return [(IRGL_PIPE_BEGIN, 1),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_INIT),
+            (IRGL_PIPE_BEGIN, 0),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_FINDMIN),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_HOOK),
+            (IRGL_PIPE_ITERATE, IRGL_BODY_MST_JUMP),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_RELABEL),
+            (IRGL_PIPE_END,),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_MINID),
+            (IRGL_PIPE_INVOKE, IRGL_BODY_MST_LABEL),
+            (IRGL_PIPE_END,)]

@@ -71,7 +71,10 @@ def query_stream(graphs, count: int, seed: int):
 
 
 def state_bytes(g) -> int:
-    """Per-query device state the caller allocates: the output array."""
+    """Per-query device state: the output array the caller allocates for the
+    query.  Everything else a running query touches (worklists, stamps, far
+    lists, bitmap) lives in the server's team scratch, allocated once when the
+    server opens and reused by every query, so it is not per-query state."""
     return 4 * g.n
 
 
@@ -98,9 +101,12 @@ def run_plain(graphs, queries, arrivals):
 
 
 def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap: int = 512,
-               keep_outputs=None):
+               keep_outputs=None, info=None):
     """Continuous batching through an open batch.  Returns latencies (s), wall
-    time, and the outputs of the queries whose indices are in keep_outputs."""
+    time, the outputs of the queries whose indices are in keep_outputs, and
+    the number rejected.  `info` (a dict), when given, receives the admission
+    record: queries that waited for memory, the peak of admitted state bytes
+    and of queries in flight."""
     hgs = [hg for _, hg in graphs]
     server = irgl.irgl_batch_open(hgs, cfg=cfg, ring_cap=ring_cap)
     dev = graphs[0][0].row_ptr.device
@@ -112,6 +118,9 @@ def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap:
     nxt = 0
     done_count = 0
     rejected = 0
+    mem_waited = set()
+    peak_used = 0
+    peak_inflight = 0
     t0 = time.perf_counter()
     while done_count + rejected < len(queries):
         now = time.perf_counter() - t0
@@ -129,6 +138,7 @@ def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap:
                 lat[qi] = np.nan
                 continue
             if used + need > budget_bytes:
+                mem_waited.add(qi)
                 break
             task = irgl.Task(hgs[gi], kind, src)
             ticket = irgl.irgl_batch_enqueue(server, task)
@@ -137,6 +147,8 @@ def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap:
             pending.popleft()
             used += need
             inflight[ticket] = (qi, task, need)
+            peak_used = max(peak_used, used)
+            peak_inflight = max(peak_inflight, len(inflight))
         for ticket in list(inflight):
             st = irgl.irgl_batch_poll(server, ticket)
             if st is not None:
@@ -157,6 +169,9 @@ def run_served(graphs, queries, arrivals, budget_bytes: int, cfg=None, ring_cap:
     wall = time.perf_counter() - t0
     server.close()
     torch.cuda.synchronize()
+    if info is not None:
+        info.update({"waited_for_memory": len(mem_waited), "peak_state_bytes": peak_used,
+                     "peak_in_flight": peak_inflight})
     return lat, wall, kept, rejected
 
 

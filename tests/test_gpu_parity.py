@@ -227,6 +227,39 @@ def test_reordered_upload(irgl):
     assert e.value.status == irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
 
 
+def test_sssp_light_heavy_split(irgl):
+    """Relabelled weighted graphs carry an SSSP copy whose rows are split into
+    light and heavy edges at the graph's step; irgl_graph_set_delta forces a
+    split on graphs too small to get one by default.  Distances equal the
+    oracle's at every step (from one that makes every edge heavy to one that
+    makes every edge light), with every block size, with parents, and with
+    the step removed again; a query at another step runs without the split."""
+    graphs = [_dev(gg.rmat(14, seed=81, weight_seed=82, wmax=255)),
+              _dev(gg.config_road(width=96)),
+              _dev(gg.uniform_random(20000, 12.0, seed=83, weight_seed=84, wmax=1000)),
+              _dev(gg.random_directed(5000, 40000, seed=85, weight_seed=86, wmax=64))]
+    for g in graphs:
+        hr = irgl.upload(g, reorder=True)
+        wmax = int(np.asarray(g.numpy()[2], dtype=np.uint32).max())
+        srcs = gg.pick_sources(g, 2, seed=87) if g.sources is None or len(g.sources) < 2 else g.sources[:2]
+        for delta in (1, 7, max(2, wmax // 4), max(2, wmax // 2), wmax + 1, 3 * wmax):
+            irgl.irgl_graph_set_delta(hr, delta)
+            assert irgl.irgl_graph_default_delta(hr) == delta
+            for src in srcs:
+                _check_query(irgl, g, hr, SSSP, src, None, with_parent=False)
+            _check_query(irgl, g, hr, SSSP, srcs[0], {"block": 256}, with_parent=True)
+            _check_query(irgl, g, hr, SSSP, srcs[0], {"block": 1024, "t_grid": 64}, with_parent=False)
+        # a query at a step other than the partition's runs unsplit
+        _check_query(irgl, g, hr, SSSP, srcs[1], {"delta": 5}, with_parent=False)
+        # the split also under the host-loop form falls back to the unsplit loop
+        _check_query(irgl, g, hr, SSSP, srcs[1], {"mode": 1}, with_parent=False)
+        irgl.irgl_graph_set_delta(hr, irgl.IRGL_DELTA_NONE)
+        assert irgl.irgl_graph_default_delta(hr) == irgl.IRGL_DELTA_NONE
+        _check_query(irgl, g, hr, SSSP, srcs[0], None, with_parent=False)
+    with pytest.raises(irgl.IrglError):
+        irgl.irgl_graph_set_delta(hr, 0)
+
+
 @pytest.mark.parametrize("reduce", [0, 1])
 def test_topology_driven_iterate(irgl, reduce):
     """IRGL_MODE_TOPOLOGY (a ForAll over every node whose invocation returns
