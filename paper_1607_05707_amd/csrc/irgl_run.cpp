@@ -5,9 +5,12 @@
 //   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
 //                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
 //                 [--do-alpha A] [--delta D] [--calibrate MB] [--reorder 0|1]
+//                 [--set-delta D]
 //
 // --calibrate MB first copies MB megabytes device-to-device once (a plain
-// copy of known traffic, to scale hardware byte counters).
+// copy of known traffic, to scale hardware byte counters).  --set-delta D
+// changes the graph's default SSSP near/far step after the upload (on a
+// relabelled weighted graph it also rebuilds the light/heavy partition).
 //
 // Prints one line per kind: queries, mean microseconds per query (hipEvent
 // pairs around each call on one stream) and GTEPS (out-degree sum of the
@@ -48,6 +51,7 @@ int main(int argc, char **argv) {
     int nsrc = 8, reps = 1, warmup = 1;
     long calib_mb = 0;
     int reorder = 0;
+    uint32_t set_delta = 0;  // irgl_graph_set_delta after the upload (0: keep the default step)
     irgl_config cfg;
     std::memset(&cfg, 0, sizeof(cfg));
     for (int i = 2; i + 1 < argc; i += 2) {
@@ -64,6 +68,7 @@ int main(int argc, char **argv) {
         else if (k == "--do-alpha") cfg.do_alpha = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--delta") cfg.delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--reorder") reorder = std::atoi(v);
+        else if (k == "--set-delta") set_delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--calibrate") calib_mb = std::atol(v);
         else {
             std::fprintf(stderr, "unknown option %s\n", k.c_str());
@@ -135,6 +140,10 @@ int main(int argc, char **argv) {
     } else {
         CI(irgl_graph_upload(&csr, &g));
     }
+    if (set_delta) CI(irgl_graph_set_delta(g, set_delta));
+    uint32_t qdelta = 0;
+    CI(irgl_graph_default_delta(g, &qdelta));
+    std::printf("default near/far step %u\n", qdelta);
     irgl_stats *d_stats;
     CK(hipMalloc(&d_stats, sizeof(irgl_stats)));
     hipStream_t s;
@@ -181,6 +190,20 @@ int main(int argc, char **argv) {
         CK(hipStreamSynchronize(s));
         irgl_stats st;
         CI(irgl_query_status(ws, s, &st));
+        // work of one more (untimed) pass: CSR entries scanned per reached edge
+        double scanned = 0;
+        for (int i = 0; i < nsrc; ++i) {
+            CI(run(src[i]));
+            irgl_stats sq;
+            CI(irgl_query_status(ws, s, &sq));
+            if (sq.status) {
+                std::fprintf(stderr, "%s from %d: %s\n", name, src[i], irgl_status_string(sq.status));
+                return 1;
+            }
+            scanned += static_cast<double>(sq.edges);
+        }
+        double mcc_sum = 0;
+        for (int i = 0; i < nsrc; ++i) mcc_sum += static_cast<double>(mcc[i]);
         double tot_ms = 0, edges = 0;
         for (int q = 0; q < nsrc * reps; ++q) {
             float ms;
@@ -188,9 +211,10 @@ int main(int argc, char **argv) {
             tot_ms += ms;
             edges += static_cast<double>(mcc[q % nsrc]);
         }
-        std::printf("%s queries=%d mean_us=%.1f gteps=%.3f status=%d iterations=%u grid=%dx%d\n", name,
-                    nsrc * reps, 1e3 * tot_ms / (nsrc * reps), edges / (tot_ms * 1e-3) / 1e9, st.status,
-                    st.iterations, st.grid, st.block);
+        std::printf("%s queries=%d mean_us=%.1f gteps=%.3f status=%d iterations=%u grid=%dx%d "
+                    "scans_per_edge=%.3f\n", name, nsrc * reps, 1e3 * tot_ms / (nsrc * reps),
+                    edges / (tot_ms * 1e-3) / 1e9, st.status, st.iterations, st.grid, st.block,
+                    mcc_sum > 0 ? scanned / mcc_sum : 0.0);
         std::fflush(stdout);
         for (auto &e : ev) CK(hipEventDestroy(e));
         CK(hipFree(ws));

@@ -100,9 +100,10 @@ def test_rmat22_sssp_full_size(irgl, rmat22):
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     ws = irgl.workspace(hg, SSSP, False, BENCH_CFG)
     stats = irgl.stats_tensor(dev)
-    # scale-free with more than 2^26 edges: the near/far step is the mean weight
+    # scale-free with more than 2^26 edges, relabelled weighted upload (rows
+    # split into light and heavy edges): the near/far step is half the mean weight
     mean_w = float(np.asarray(w, dtype=np.uint32).astype(np.uint64).sum()) / g.m
-    assert irgl.irgl_graph_default_delta(hg) == int(mean_w)
+    assert irgl.irgl_graph_default_delta(hg) == int(0.5 * mean_w)
     compare = (0, 31, 63)
     for i in range(64):
         src = g.sources[i]
@@ -178,7 +179,8 @@ def test_road4096_full_size(irgl, long_edges):
                 np.testing.assert_array_equal(got, ref, err_msg=f"{g.name} kind={kind}")
             if kind == BFS:
                 assert st["iterations"] == int(got[got != oracle.INF].max()) + 1
-                if not long_edges:
+                if not long_edges and i == 0:
+                    # from the corner the high-diameter grid has ~8,190 levels
                     assert st["iterations"] > 8000
 
 
