@@ -16,6 +16,10 @@ HIP library and never calls it.
   (``oracle_certify``), fast enough to check every full-size output.
 * ``edges_scanned``: the TEPS numerator, the out-degree sum of the reached
   vertices (pinned by closed forms).
+* ``mesh.check_mesh``: the complete validity check of a refined mesh for the
+  Delaunay mesh refinement workload of the Exclusive construct (Section 3):
+  conformity, Delaunay, quality bound, no encroached boundary edge, input
+  points kept (``oracle/mesh.py``).
 """
 from __future__ import annotations
 
