@@ -321,6 +321,27 @@ irgl_status irgl_bfs(irgl_graph g, int32_t src, uint32_t *level, int32_t *parent
 irgl_status irgl_sssp(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent, void *ws,
                       size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_config *cfg);
 
+/* irgl_sssp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * query's workspace is a device array of IRGL_NOALLOC_SCRATCH_BYTES that the
+ * library holds (one per device, from the library's load until the process
+ * ends).  The call allocates nothing: no hipMalloc / hipFree, no allocating
+ * library routine; the caller still passes the outputs (dist, parent, dstats
+ * as for irgl_sssp).  Every call on one device shares that device's array,
+ * and each query resets what it reads before the kernel uses it, so calls
+ * that run one after another need nothing cleared; calls that OVERLAP on one
+ * device (on different streams, or from different threads without ordering)
+ * race on the array and give undefined results.  The statistics of a query
+ * are read through dstats (irgl_query_status needs the workspace address).
+ * Errors: as irgl_sssp; IRGL_ERR_TOO_LARGE when the query's workspace
+ * (irgl_workspace_bytes for the same graph, config and parent choice) exceeds
+ * IRGL_NOALLOC_SCRATCH_BYTES (64 MiB: up to about 1.3M vertices with the
+ * default config); IRGL_ERR_CONFIG for IRGL_MODE_HOST_LOOP (its read-back
+ * word is allocated on first use). */
+#define IRGL_NOALLOC_SCRATCH_BYTES (64u << 20)
+irgl_status irgl_sssp_noalloc(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent, void *stream,
+                              irgl_stats *dstats, const irgl_config *cfg);
+
 /* Synchronize `stream`, then copy the statistics of the last query that used
  * workspace `ws` into host memory *out (status, iterations, counters). */
 irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out);

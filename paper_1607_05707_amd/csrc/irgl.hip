@@ -996,6 +996,40 @@ irgl_status reorder_layout(int32_t n, int64_t m, bool weighted, ReorderLayout *o
     return IRGL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The library's own query workspace, for callers that cannot allocate
+// (irgl_sssp_noalloc).  Every device the library runs on holds one copy of
+// the array until the process ends.  In host code `scratch` names a host-side
+// stand-in, not a device address: the device address of each device's copy
+// is taken once per device with hipGetSymbolAddress (that device current) and
+// only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t{IRGL_NOALLOC_SCRATCH_BYTES};
+static_assert(kScratchBytes % kAlign == 0, "scratch size");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+irgl_status scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return IRGL_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        IRGL_HIP(hipGetDevice(&cur));
+        if (cur != dev) IRGL_HIP(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e);
+        if (!ptr) return IRGL_ERR_DEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return IRGL_OK;
+}
+
 }  // namespace
 
 // For the library's other translation units (the Boruvka workload): the
@@ -1269,6 +1303,26 @@ irgl_status irgl_bfs(irgl_graph g, int32_t src, uint32_t *level, int32_t *parent
 irgl_status irgl_sssp(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent, void *ws,
                       size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_config *cfg) {
     return run(IRGL_KIND_SSSP, g, src, dist, parent, ws, ws_bytes, stream, dstats, cfg);
+}
+
+irgl_status irgl_sssp_noalloc(irgl_graph g, int32_t src, uint32_t *dist, int32_t *parent, void *stream,
+                              irgl_stats *dstats, const irgl_config *cfg) {
+    if (!g || !dist) return IRGL_ERR_INVALID_ARGUMENT;
+    if (src < 0 || src >= g->n) return IRGL_ERR_INVALID_ARGUMENT;
+    if (!g->w) return IRGL_ERR_NO_WEIGHTS;
+    Cfg c;
+    irgl_status st = resolve(g, IRGL_KIND_SSSP, cfg, &c);
+    if (st) return st;
+    // the host-loop form reads worklist sizes back through a pinned host
+    // word that the library allocates on a thread's first such query
+    if (c.mode == IRGL_MODE_HOST_LOOP) return IRGL_ERR_CONFIG;
+    if (layout(g, IRGL_KIND_SSSP, c, parent != nullptr).total > kScratchBytes) return IRGL_ERR_TOO_LARGE;
+    void *ws = nullptr;
+    st = scratch_address(g->device, &ws);
+    if (st) return st;
+    // run() lays the workspace out exactly as for irgl_sssp; init_kernel
+    // resets every part of it the query reads before writing it
+    return run(IRGL_KIND_SSSP, g, src, dist, parent, ws, kScratchBytes, stream, dstats, cfg);
 }
 
 irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out) {

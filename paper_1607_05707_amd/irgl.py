@@ -147,6 +147,8 @@ for _name in ("irgl_bfs", "irgl_sssp"):
     _f = getattr(_lib, _name)
     _f.restype = ctypes.c_int32
     _f.argtypes = [_c, ctypes.c_int32, _c, _c, _c, ctypes.c_size_t, _c, _c, ctypes.POINTER(irgl_config)]
+_lib.irgl_sssp_noalloc.restype = ctypes.c_int32
+_lib.irgl_sssp_noalloc.argtypes = [_c, ctypes.c_int32, _c, _c, _c, _c, ctypes.POINTER(irgl_config)]
 _lib.irgl_wallclock_khz.restype = ctypes.c_int32
 _lib.irgl_wallclock_khz.argtypes = [ctypes.POINTER(ctypes.c_int32)]
 _lib.irgl_query_status.restype = ctypes.c_int32
@@ -355,6 +357,23 @@ def irgl_sssp(g: Graph, src: int, dist: torch.Tensor, parent: Optional[torch.Ten
               cfg=None) -> None:
     """Asynchronous SSSP from src on `stream`; dist is a device int32/uint32 [n]."""
     _run(_lib.irgl_sssp, "irgl_sssp", g, src, dist, parent, ws, stream, stats, cfg)
+
+
+IRGL_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def irgl_sssp_noalloc(g: Graph, src: int, dist: torch.Tensor, parent: Optional[torch.Tensor] = None,
+                      stream=None, stats: Optional[torch.Tensor] = None, cfg=None) -> None:
+    """irgl_sssp on the library's own device scratch (no workspace argument,
+    nothing allocated); calls that overlap on one device race."""
+    if g.handle is None:
+        raise ValueError("graph handle was freed")
+    op = _dev_ptr(dist, "dist", _I32, g.n)
+    pp = _dev_ptr(parent, "parent", _I32, g.n)
+    sp = _dev_ptr(stats, "stats", (torch.uint8,), STATS_BYTES) if stats is not None else None
+    cp, _keep = _cfg_ptr(cfg)
+    _check(_lib.irgl_sssp_noalloc(g.handle, int(src), op, pp, _stream_handle(stream), sp, cp),
+           "irgl_sssp_noalloc")
 
 
 def irgl_query_status(ws: torch.Tensor, stream=None) -> dict:
