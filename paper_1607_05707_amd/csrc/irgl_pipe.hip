@@ -8,10 +8,14 @@
 //
 // Pipe context.  Three worklist buffers play the roles in / out / retry.  An
 // invocation pops `in` and pushes `out` and `retry`; the counts it produces
-// live in rotating counters indexed by the invocation number (invocation i
-// pushes through cnt[i % 3] and clears cnt[(i + 2) % 3], which nobody reads
-// again before the next barrier).  Every workgroup keeps the roles and the
-// counts of the context in registers:
+// live in rotating counters indexed by the invocation number.  Invocation i
+// pushes through cnt[i % 3], which every workgroup reads right after the
+// barrier that ends i, and clears cnt[(i + 1) % 3] for the next invocation:
+// that counter was last read after the barrier ending i - 2, before each
+// workgroup arrived at the barrier ending i - 1.  (Clearing cnt[(i + 2) % 3]
+// would let a workgroup that starts invocation i + 1 early clear the count
+// of i while a slower workgroup has yet to read it.)  Every workgroup keeps
+// the roles and the counts of the context in registers:
 //   - after a body that uses worklists: in <-> out, |in| = |out|;
 //   - after a body that uses `retry` with a non-empty retry list: in <-> retry
 //     and the body runs again; `out` keeps filling (its base offset grows);
@@ -417,9 +421,9 @@ __device__ bool invoke(const Params &p, PipeSmem<B> &sm, int *s_flag, Team tm, B
         }
         const uint32_t i = s.inv;
         if (lead) {
-            store_agent(&p.cnt->out[(i + 2) % 3], 0u);
-            store_agent(&p.cnt->retry[(i + 2) % 3], 0u);
-            store_agent(&p.cnt->red[(i + 2) % 3], 0u);
+            store_agent(&p.cnt->out[(i + 1) % 3], 0u);
+            store_agent(&p.cnt->retry[(i + 1) % 3], 0u);
+            store_agent(&p.cnt->red[(i + 1) % 3], 0u);
             if (i < p.trace_len) p.trace[i] = body;
         }
         if (bi.uses_wl) {
