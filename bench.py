@@ -382,6 +382,50 @@ def road_section(dev, stream, reps=2):
     return res
 
 
+def dmr_section(args, dev):
+    """Delaunay mesh refinement (the Exclusive construct's workload, one
+    cooperative launch running the DMR pipe) of a random-square mesh: time
+    per refinement, points inserted and triangles made per second, and the
+    oracle's validity check of one refined mesh."""
+    import torch
+    from paper_1607_05707_amd import irgl, meshgen
+    t0 = time.perf_counter()
+    m = meshgen.random_square(args.dmr_points, 42)
+    log(f"dmr mesh {m.name}: {m.npts} points, {m.ntri} triangles, generated in {time.perf_counter() - t0:.1f}s")
+    best, st, dm = float("inf"), None, None
+    for _ in range(args.dmr_reps):
+        dm = irgl.DeviceMesh.from_host(m, dev)
+        ws = torch.empty(irgl.irgl_dmr_workspace_bytes(dm), dtype=torch.uint8, device=dev)
+        stats = torch.zeros(irgl.DMR_STATS_BYTES, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        irgl.irgl_dmr_refine(dm, ws, None, None, stats)
+        b.record()
+        torch.cuda.synchronize()
+        st = irgl.read_dmr_stats(stats)
+        if st["status"] != 0:
+            raise SystemExit(f"dmr failed: {irgl.irgl_status_string(st['status'])}")
+        best = min(best, a.elapsed_time(b))
+    res = {"mesh": m.name, "input_points": m.npts, "input_triangles": m.ntri, "min_angle": 30.0,
+           "ms": round(best, 2), "points": st["npts"], "triangles": st["ntri"],
+           "inserted": st["inserted"], "splits": st["splits"], "invocations": st["invocations"],
+           "rounds": st["rounds"], "refined": st["refined"], "conflicts": st["conflicts"],
+           "max_cavity": st["max_cavity"], "final_bad": st["final_bad"],
+           "mpoints_per_s": round((st["npts"] - m.npts) / (best / 1e3) / 1e6, 2),
+           "mtriangles_per_s": round(st["ntri"] / (best / 1e3) / 1e6, 2)}
+    if not args.no_dmr_check:
+        from oracle import mesh as om
+        t0 = time.perf_counter()
+        chk = om.check_mesh(dm.pts[:st["npts"]].cpu().numpy(), dm.tri[:st["ntri"]].cpu().numpy(),
+                            dm.nbr[:st["ntri"]].cpu().numpy(), input_pts=m.input_pts, min_angle=30.0)
+        res["oracle_check"] = {"valid": True, "min_angle": round(chk["min_angle"], 4),
+                               "seconds": round(time.perf_counter() - t0, 1)}
+    log(f"dmr {res}")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,6 +457,10 @@ def main() -> int:
     ap.add_argument("--serve-burst", type=int, default=600)
     ap.add_argument("--serve-small-budget-mb", type=int, default=96)
     ap.add_argument("--no-levels", action="store_true", help="skip the grid64 / road4096 legs")
+    ap.add_argument("--no-dmr", action="store_true", help="skip the mesh-refinement leg")
+    ap.add_argument("--no-dmr-check", action="store_true", help="skip the oracle check of the refined mesh")
+    ap.add_argument("--dmr-points", type=int, default=1000000)
+    ap.add_argument("--dmr-reps", type=int, default=3)
     ap.add_argument("--calibrate-mb", type=int, default=0,
                     help="first copy this many MiB device to device once (a copy of known traffic that "
                          "scales hardware byte counters)")
@@ -595,6 +643,10 @@ def main() -> int:
                   "road4096_nolong": level_section(dev, stream, "road4096_nolong", reps=1),
                   "road4096": road_section(dev, stream)}
 
+    dmr = None
+    if not args.no_dmr:
+        dmr = dmr_section(args, dev)
+
     names = {0: "bfs", 1: "sssp"}
     line = {
         "metric": "GTEPS BFS/SSSP on RMAT-22, batched vs plain; HBM GB/s; p99 query latency",
@@ -630,6 +682,7 @@ def main() -> int:
         "topology": topology,
         "mst": mst,
         "levels": levels,
+        "dmr": dmr,
     }
     print(json.dumps(line), flush=True)
     return 0

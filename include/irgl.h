@@ -645,6 +645,86 @@ irgl_status irgl_mst_workspace_bytes(irgl_graph g, size_t *bytes);
 irgl_status irgl_mst(irgl_graph g, uint64_t *weight, int32_t *component, uint8_t *in_forest, void *ws,
                      size_t ws_bytes, void *stream, irgl_stats *dstats, const irgl_mst_config *cfg);
 
+/* ---------------------------------------------------------------------
+ * Delaunay mesh refinement: the workload of the Exclusive construct
+ * (Section 3, Exclusive: the refine kernel, whose item must own every
+ * triangle of its bad triangle's cavity and every triangle bordering it;
+ * the locks are taken in three phases, race / priority check / check,
+ * separated by grid barriers, and an item that loses goes back to the
+ * worklist) and of the Pipe of the DMR main loop (Section 4.2: identify
+ * the bad triangles once, then a looping Pipe of refine and incremental
+ * identification among the triangles refine created, then one more
+ * identification as a sanity check), all in ONE cooperative launch.
+ *
+ * The mesh triangulates the unit square [0,1]^2 and is Delaunay on entry
+ * (the generators in meshgen.py build such meshes).  A triangle needs work
+ * when its smallest angle is below the bound or when one of its boundary
+ * edges is encroached (its opposite vertex sees it at more than 90
+ * degrees).  Refinement inserts the circumcentre of a bad triangle, or, when
+ * that point falls outside the domain or inside the diametral circle of a
+ * boundary edge, the midpoint of that edge; the new point's cavity is
+ * re-triangulated (Bowyer-Watson), so the mesh stays Delaunay.  On success
+ * no triangle needs work; the result is not unique (it depends on the
+ * order of insertions).
+ * --------------------------------------------------------------------- */
+typedef struct irgl_mesh {
+    double *pts;    /* DEVICE float64[pcap][2]: x, y; the first npts in use */
+    int32_t *tri;   /* DEVICE int32[tcap][4]: v0, v1, v2 (counter-clockwise), live flag */
+    int32_t *nbr;   /* DEVICE int32[tcap][4]: entry i = the triangle across edge
+                       (v_i, v_(i+1) mod 3), -1 on the domain boundary; entry 3 unused */
+    int32_t npts;   /* points in use on entry (>= 3) */
+    int32_t ntri;   /* triangle slots in use on entry (>= 1), all live */
+    int32_t pcap;   /* capacity of pts (rows) */
+    int32_t tcap;   /* capacity of tri and nbr (rows), below 2^30 */
+} irgl_mesh;
+
+typedef struct irgl_dmr_config {
+    double min_angle;          /* quality bound in degrees, in (0, 60); 0 = 30 */
+    int32_t block;             /* 64, 128 or 256 (default) threads per workgroup */
+    int32_t grid;              /* workgroups; 0 = co-resident limit */
+    uint32_t max_invocations;  /* safety cap of kernel invocations (0 = 100000) */
+    uint32_t watchdog_ms;      /* bound of every barrier wait (0 = 20000) */
+    uint32_t barrier;          /* IRGL_BARRIER_* */
+    uint32_t reserved;
+} irgl_dmr_config;
+
+/* Written by the device when the refinement ends. */
+typedef struct irgl_dmr_stats {
+    int32_t status;          /* irgl_status of the run */
+    uint32_t invocations;    /* kernel invocations of the pipe */
+    uint32_t rounds;         /* Exclusive rounds (three phases each) over all refine invocations */
+    int32_t block;
+    int32_t grid;
+    uint32_t reserved;
+    uint64_t refined;        /* worklist items popped by refine */
+    uint64_t conflicts;      /* items that lost their Exclusive section (Else: retried) */
+    uint32_t inserted;       /* circumcentres inserted */
+    uint32_t splits;         /* boundary edges split at their midpoint */
+    int32_t npts;            /* points in use at the end */
+    int32_t ntri;            /* triangle slots in use at the end (all live) */
+    uint32_t final_bad;      /* triangles needing work found by the final identification (0 on success) */
+    uint32_t max_cavity;     /* largest cavity re-triangulated */
+} irgl_dmr_stats;
+
+/* Device workspace bytes of irgl_dmr_refine on a mesh of this capacity:
+ * the pipe's two worklists, the lock and push-stamp words (one per triangle
+ * slot) and the control block.  Errors: INVALID_ARGUMENT (null pointers,
+ * npts < 3, ntri < 1, capacities below the counts or at least 2^30). */
+irgl_status irgl_dmr_workspace_bytes(const irgl_mesh *m, size_t *bytes);
+
+/* Refine *m in place, asynchronously on `stream`: points are appended after
+ * npts (the input points keep their indices and coordinates), triangles are
+ * rewritten in their slots and appended after ntri; the final counts are in
+ * dstats (DEVICE irgl_dmr_stats, optional).  ws: DEVICE, at least
+ * irgl_dmr_workspace_bytes.  Errors: as irgl_dmr_workspace_bytes,
+ * WORKSPACE_TOO_SMALL, CONFIG (angle, block, grid, barrier); on the device
+ * (dstats.status) OVERFLOW when the point or triangle capacity or a cavity
+ * bound (64 triangles) is exceeded, ITERATION_LIMIT, WATCHDOG, INTERNAL when
+ * a geometric step fails (a point location that does not end, a cavity that
+ * is not star-shaped); the mesh is then not valid. */
+irgl_status irgl_dmr_refine(const irgl_mesh *m, void *ws, size_t ws_bytes, const irgl_dmr_config *cfg, void *stream,
+                            irgl_dmr_stats *dstats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ LIB = os.path.join(LIBDIR, "libirgl.so")
 RUNNER = os.path.join(LIBDIR, "irgl_run")
 ARCH = os.environ.get("IRGL_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["irgl.hip", "irgl_mst.hip", "irgl_pipe.hip"]
+SOURCES = ["irgl.hip", "irgl_mst.hip", "irgl_pipe.hip", "irgl_dmr.hip"]
 
 
 def hipcc() -> str:

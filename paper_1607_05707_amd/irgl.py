@@ -924,3 +924,115 @@ def pipe_boruvka_program():
             (IRGL_PIPE_INVOKE, IRGL_BODY_MST_MINID),
             (IRGL_PIPE_INVOKE, IRGL_BODY_MST_LABEL),
             (IRGL_PIPE_END,)]
+
+
+# ---------------------------------------------------------------------------
+# Delaunay mesh refinement (the Exclusive construct's workload).
+# ---------------------------------------------------------------------------
+
+class irgl_mesh(ctypes.Structure):
+    _fields_ = [("pts", ctypes.c_void_p), ("tri", ctypes.c_void_p), ("nbr", ctypes.c_void_p),
+                ("npts", ctypes.c_int32), ("ntri", ctypes.c_int32), ("pcap", ctypes.c_int32),
+                ("tcap", ctypes.c_int32)]
+
+
+class irgl_dmr_config(ctypes.Structure):
+    _fields_ = [("min_angle", ctypes.c_double), ("block", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("max_invocations", ctypes.c_uint32), ("watchdog_ms", ctypes.c_uint32),
+                ("barrier", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class irgl_dmr_stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("invocations", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("block", ctypes.c_int32), ("grid", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("refined", ctypes.c_uint64), ("conflicts", ctypes.c_uint64), ("inserted", ctypes.c_uint32),
+                ("splits", ctypes.c_uint32), ("npts", ctypes.c_int32), ("ntri", ctypes.c_int32),
+                ("final_bad", ctypes.c_uint32), ("max_cavity", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+DMR_STATS_BYTES = ctypes.sizeof(irgl_dmr_stats)
+
+_lib.irgl_dmr_workspace_bytes.restype = ctypes.c_int32
+_lib.irgl_dmr_workspace_bytes.argtypes = [ctypes.POINTER(irgl_mesh), ctypes.POINTER(ctypes.c_size_t)]
+_lib.irgl_dmr_refine.restype = ctypes.c_int32
+_lib.irgl_dmr_refine.argtypes = [ctypes.POINTER(irgl_mesh), _c, ctypes.c_size_t, ctypes.POINTER(irgl_dmr_config),
+                                 _c, _c]
+
+
+class DeviceMesh:
+    """A mesh resident on the device (tensors owned here): pts float64
+    [pcap, 2], tri and nbr int32 [tcap, 4], plus the counts in use."""
+
+    def __init__(self, pts: torch.Tensor, tri: torch.Tensor, nbr: torch.Tensor, npts: int, ntri: int):
+        self.pts, self.tri, self.nbr = pts, tri, nbr
+        self.npts, self.ntri = int(npts), int(ntri)
+
+    @classmethod
+    def from_host(cls, m, device) -> "DeviceMesh":
+        """From a meshgen.Mesh (host arrays sized to their capacities)."""
+        return cls(torch.from_numpy(m.pts).to(device), torch.from_numpy(m.tri).to(device),
+                   torch.from_numpy(m.nbr).to(device), m.npts, m.ntri)
+
+    def c_struct(self) -> irgl_mesh:
+        s = irgl_mesh()
+        s.pts = _dev_ptr(self.pts, "pts", (torch.float64,))
+        s.tri = _dev_ptr(self.tri, "tri", (torch.int32,))
+        s.nbr = _dev_ptr(self.nbr, "nbr", (torch.int32,))
+        if self.pts.dim() != 2 or self.pts.shape[1] != 2:
+            raise ValueError("pts must be [pcap, 2]")
+        if self.tri.dim() != 2 or self.tri.shape[1] != 4 or self.nbr.shape != self.tri.shape:
+            raise ValueError("tri and nbr must be [tcap, 4]")
+        s.npts, s.ntri = self.npts, self.ntri
+        s.pcap, s.tcap = int(self.pts.shape[0]), int(self.tri.shape[0])
+        return s
+
+
+def _dmr_config(cfg):
+    if cfg is None or isinstance(cfg, irgl_dmr_config):
+        return cfg
+    c = irgl_dmr_config()
+    for k, v in dict(cfg).items():
+        setattr(c, k, float(v) if k == "min_angle" else int(v))
+    return c
+
+
+def irgl_dmr_workspace_bytes(mesh: DeviceMesh) -> int:
+    out = ctypes.c_size_t()
+    s = mesh.c_struct()
+    _check(_lib.irgl_dmr_workspace_bytes(ctypes.byref(s), ctypes.byref(out)), "irgl_dmr_workspace_bytes")
+    return int(out.value)
+
+
+def irgl_dmr_refine(mesh: DeviceMesh, ws: torch.Tensor, cfg=None, stream=None,
+                    stats: Optional[torch.Tensor] = None) -> None:
+    """Asynchronous refinement of `mesh` in place on `stream`."""
+    s = mesh.c_struct()
+    c = _dmr_config(cfg)
+    sp = _dev_ptr(stats, "stats", (torch.uint8,), DMR_STATS_BYTES) if stats is not None else None
+    _check(_lib.irgl_dmr_refine(ctypes.byref(s), _dev_ptr(ws, "ws", (torch.uint8,)), ws.numel(),
+                                ctypes.byref(c) if c is not None else None, _stream_handle(stream), sp),
+           "irgl_dmr_refine")
+
+
+def read_dmr_stats(buf: torch.Tensor) -> dict:
+    raw = bytes(buf.cpu().numpy().tobytes())
+    return irgl_dmr_stats.from_buffer_copy(raw).as_dict()
+
+
+def dmr(mesh: DeviceMesh, cfg=None, stream=None) -> dict:
+    """Refine synchronously; updates mesh.npts / mesh.ntri and returns the
+    statistics (raises IrglError on a device-side error)."""
+    dev = mesh.pts.device
+    ws = torch.empty(irgl_dmr_workspace_bytes(mesh), dtype=torch.uint8, device=dev)
+    stats = torch.zeros(DMR_STATS_BYTES, dtype=torch.uint8, device=dev)
+    irgl_dmr_refine(mesh, ws, cfg, stream, stats)
+    if stream is not None:
+        stream.synchronize()
+    st = read_dmr_stats(stats)
+    if st["status"] != IRGL_OK:
+        raise IrglError(st["status"], "device")
+    mesh.npts, mesh.ntri = st["npts"], st["ntri"]
+    return st

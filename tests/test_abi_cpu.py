@@ -97,7 +97,9 @@ def test_ctypes_layouts_match_the_header(tmp_path):
     from paper_1607_05707_amd import irgl
     structs = {"irgl_csr": irgl.irgl_csr, "irgl_config": irgl.irgl_config, "irgl_stats": irgl.irgl_stats,
                "irgl_mst_config": irgl.irgl_mst_config,
-               "irgl_task": irgl.irgl_task, "irgl_batch_config": irgl.irgl_batch_config}
+               "irgl_task": irgl.irgl_task, "irgl_batch_config": irgl.irgl_batch_config,
+               "irgl_mesh": irgl.irgl_mesh, "irgl_dmr_config": irgl.irgl_dmr_config,
+               "irgl_dmr_stats": irgl.irgl_dmr_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "irgl.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
@@ -132,3 +134,28 @@ def test_batch_argument_errors_without_device():
     assert L.irgl_batch_submit(arr, 0, 0x1000, 100, None, None, ctypes.byref(h)) == irgl.IRGL_ERR_INVALID_ARGUMENT
     assert L.irgl_batch_wait(None, None) == irgl.IRGL_ERR_INVALID_ARGUMENT
     assert L.irgl_batch_free(None) == irgl.IRGL_OK
+
+
+def test_dmr_argument_errors_without_device():
+    from paper_1607_05707_amd import irgl
+    L = irgl._lib
+    INV = irgl.IRGL_ERR_INVALID_ARGUMENT
+    out = ctypes.c_size_t()
+    assert L.irgl_dmr_workspace_bytes(None, ctypes.byref(out)) == INV
+    m = irgl.irgl_mesh()
+    m.pts, m.tri, m.nbr = 0x1000, 0x2000, 0x3000
+    for npts, ntri, pcap, tcap in [(2, 1, 10, 10), (3, 0, 10, 10), (5, 1, 4, 10), (5, 4, 10, 3),
+                                   (5, 4, 10, 1 << 30)]:
+        m.npts, m.ntri, m.pcap, m.tcap = npts, ntri, pcap, tcap
+        assert L.irgl_dmr_workspace_bytes(ctypes.byref(m), ctypes.byref(out)) == INV, (npts, ntri, pcap, tcap)
+    m.npts, m.ntri, m.pcap, m.tcap = 4, 2, 16, 16
+    assert L.irgl_dmr_workspace_bytes(ctypes.byref(m), ctypes.byref(out)) == irgl.IRGL_OK
+    assert L.irgl_dmr_refine(ctypes.byref(m), None, 0, None, None, None) == INV
+    assert L.irgl_dmr_refine(ctypes.byref(m), 0x4000, out.value - 1, None, None, None) == \
+        irgl.IRGL_ERR_WORKSPACE_TOO_SMALL
+    cfg = irgl.irgl_dmr_config()
+    for field, value in (("min_angle", 60.0), ("block", 512)):
+        cfg = irgl.irgl_dmr_config()
+        setattr(cfg, field, value)
+        assert L.irgl_dmr_refine(ctypes.byref(m), 0x4000, out.value, ctypes.byref(cfg), None, None) == \
+            irgl.IRGL_ERR_CONFIG, field

@@ -234,3 +234,19 @@ def test_served_workload_full_size(irgl):
         ref = oracle.bfs(rp, col, src, with_parent=False)[0] if kind == BFS else \
             oracle.dijkstra(rp, col, w, src, with_parent=False)[0]
         np.testing.assert_array_equal(irgl.as_u32_numpy(kept[qi]), ref, err_msg=f"served query {qi}")
+
+
+def test_dmr_full_size(irgl):
+    # the benchmark's mesh refinement: 1M random points in the unit square
+    # (2M triangles), default configuration (30 degrees, 256-thread
+    # workgroups, co-resident grid); the whole refined mesh is checked
+    from oracle import mesh as om
+    from paper_1607_05707_amd import meshgen
+    m = meshgen.random_square(1_000_000, 42)
+    _say(f"dmr {m.name}: {m.npts} points, {m.ntri} triangles, default configuration")
+    dm = irgl.DeviceMesh.from_host(m, torch.device("cuda:0"))
+    st = irgl.dmr(dm)
+    assert st["final_bad"] == 0 and st["block"] == 256
+    res = om.check_mesh(dm.pts[:dm.npts].cpu().numpy(), dm.tri[:dm.ntri].cpu().numpy(),
+                        dm.nbr[:dm.ntri].cpu().numpy(), input_pts=m.input_pts, min_angle=30.0)
+    assert res["triangles"] == dm.ntri > 4 * m.ntri
