@@ -107,6 +107,8 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.do_alpha = 0;
     p.do_beta = 0;
     p.m = 0;
+    p.reduce_all = 0;
+    p.tail_div = 0;  // without the split the bucketing runs to its end
     return p;
 }
 

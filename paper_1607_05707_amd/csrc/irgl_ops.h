@@ -91,6 +91,11 @@ struct Params {
     const int32_t *inv;
     uint32_t *out_caller;
     int32_t *parent_caller;
+    // SSSP on a split scale-free graph: a threshold raise that finds fewer
+    // than (items popped so far) / tail_div vertices on the far list ends the
+    // bucketing (threshold = INF: the rest runs in plain Bellman-Ford order);
+    // 0 = never
+    uint32_t tail_div;
 };
 
 // ---------------------------------------------------------------------------

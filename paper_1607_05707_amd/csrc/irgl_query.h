@@ -411,9 +411,15 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1.
             // With an empty far list (only a heavy pass left) the threshold
             // rises by one step, so the heavy results keep their bucket order.
-            const uint32_t t_new =
+            uint32_t t_new =
                 far_n ? next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta)
                       : raise_threshold(thresh, p.delta);
+            // the last buckets of a scale-free graph hold few vertices each,
+            // and each costs invocations (barriers): once the far list is
+            // small next to the work done, finish without a threshold
+            if (p.tail_div && far_n &&
+                static_cast<unsigned long long>(far_n) * p.tail_div < r.items)
+                t_new = kInf;
             if (p.visited && r.items - refreshed >= p.t_bitmap) {
                 refresh_bitmap(p, tm, thresh);  // every distance below thresh is final
                 refreshed = r.items;

@@ -5,12 +5,15 @@
 //   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
 //                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
 //                 [--do-alpha A] [--delta D] [--calibrate MB] [--reorder 0|1]
-//                 [--set-delta D]
+//                 [--set-delta D] [--maps FILE]
 //
 // --calibrate MB first copies MB megabytes device-to-device once (a plain
 // copy of known traffic, to scale hardware byte counters).  --set-delta D
 // changes the graph's default SSSP near/far step after the upload (on a
 // relabelled weighted graph it also rebuilds the light/heavy partition).
+// --maps FILE copies the process's memory map (/proc/self/maps) to FILE
+// just before main returns, so that an address reported by a fault after
+// main (in a library destructor at exit) can be attributed to a library.
 //
 // Prints one line per kind: queries, mean microseconds per query (hipEvent
 // pairs around each call on one stream) and GTEPS (out-degree sum of the
@@ -52,6 +55,7 @@ int main(int argc, char **argv) {
     long calib_mb = 0;
     int reorder = 0;
     uint32_t set_delta = 0;  // irgl_graph_set_delta after the upload (0: keep the default step)
+    std::string maps_out;
     irgl_config cfg;
     std::memset(&cfg, 0, sizeof(cfg));
     for (int i = 2; i + 1 < argc; i += 2) {
@@ -69,6 +73,7 @@ int main(int argc, char **argv) {
         else if (k == "--delta") cfg.delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--reorder") reorder = std::atoi(v);
         else if (k == "--set-delta") set_delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--maps") maps_out = v;
         else if (k == "--calibrate") calib_mb = std::atol(v);
         else {
             std::fprintf(stderr, "unknown option %s\n", k.c_str());
@@ -228,5 +233,18 @@ int main(int argc, char **argv) {
     CK(hipFree(d_out));
     if (d_w) CK(hipFree(d_w));
     CI(irgl_shutdown());
+    if (!maps_out.empty()) {
+        FILE *in = std::fopen("/proc/self/maps", "r");
+        FILE *out = std::fopen(maps_out.c_str(), "w");
+        if (in && out) {
+            char buf[4096];
+            size_t k;
+            while ((k = std::fread(buf, 1, sizeof(buf), in)) > 0) std::fwrite(buf, 1, k, out);
+        }
+        if (in) std::fclose(in);
+        if (out) std::fclose(out);
+    }
+    std::printf("runner done\n");
+    std::fflush(stdout);
     return 0;
 }
