@@ -166,10 +166,11 @@ typedef struct irgl_config {
                              risen past them.  0 = the default, from the shape of
                              a graph uploaded with IRGL_VALIDATE (mean weight W,
                              mean out-degree D, largest out-degree X): D < 8:
-                             32 W / D; D >= 8 and X <= 16 D: 16 W / D; D >= 8,
-                             X > 16 D and at least 2^26 edges: W (W / 2 on a
-                             relabelled upload, whose SSSP copy is partitioned
-                             into light and heavy edges at that step);
+                             32 W / D; D >= 8 and X <= 16 D: 16 W / D; D >= 8
+                             and X > 16 D (scale-free): W from 2^26 edges on;
+                             on a relabelled weighted upload, whose SSSP copy
+                             is partitioned into light and heavy edges at the
+                             step, W / 4 from 2^25 edges and W / 2 from 2^24;
                              otherwise (and without IRGL_VALIDATE)
                              IRGL_DELTA_NONE (plain Bellman-Ford order).  A
                              vertex whose distance has not changed since its

@@ -141,9 +141,16 @@ bool scale_free(const irgl_graph_s *g);
 // Far-list divisor of the bucketing's early end on split scale-free graphs.
 constexpr uint32_t kTailDiv = 16;
 // Step of the light/heavy partition on a scale-free graph, as a fraction of
-// the mean weight: each heavy edge is then relaxed once, while a smaller
-// step adds buckets (one barrier each).
-constexpr double kSplitDeltaScale = 0.5;
+// the mean weight W: each heavy edge is then relaxed once, while a smaller
+// step adds buckets (one barrier each).  Measured on R-MAT graphs of scales
+// 18 to 23 (16 sources each, ms per query), the larger the graph the
+// smaller the best step: from 2^25 edges W/4 (scale 21: 2.32 against 3.01
+// without a step, scale 22: 3.53 against 5.02, scale 23: 5.93 against 8.95;
+// each within 2% of the best step tried), from 2^24 edges W/2 (scale 20:
+// 1.83 against 2.06), below that no step (scale 18: 1.10 against 1.45).
+constexpr double kSplitDeltaScale = 0.25;
+constexpr int64_t kSplitQuarterMinEdges = int64_t(1) << 25;
+constexpr int64_t kSplitHalfMinEdges = int64_t(1) << 24;
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Per-device facts, looked up once.
@@ -853,9 +860,13 @@ uint32_t delta_rule(const irgl_graph_s *g, bool partitioned) {
         d = kDeltaScale * mean_w / std::max(1.0, mean_deg);
     } else if (static_cast<double>(g->max_degree) <= kSkew * mean_deg) {
         d = kDeltaDenseScale * mean_w / mean_deg;
+    } else if (partitioned) {
+        if (g->m >= kSplitQuarterMinEdges) d = kSplitDeltaScale * mean_w;
+        else if (g->m >= kSplitHalfMinEdges) d = 2.0 * kSplitDeltaScale * mean_w;
+        else return IRGL_DELTA_NONE;
     } else {
         if (g->m < kDeltaSkewMinEdges) return IRGL_DELTA_NONE;
-        d = partitioned ? kSplitDeltaScale * mean_w : mean_w;
+        d = mean_w;
     }
     return static_cast<uint32_t>(std::min(4.0e9, std::max(1.0, d)));
 }

@@ -15,6 +15,11 @@
 // just before main returns, so that an address reported by a fault after
 // main (in a library destructor at exit) can be attributed to a library.
 //
+// FILE may also be a mesh file written by paper_1607_05707_amd.meshgen: the
+// runner then refines it (irgl_dmr_refine) `--reps` times after `--warmup`
+// untimed runs, each on a fresh copy, and prints the mean time and the
+// statistics of the last run.
+//
 // Prints one line per kind: queries, mean microseconds per query (hipEvent
 // pairs around each call on one stream) and GTEPS (out-degree sum of the
 // vertices a BFS from each source reaches / time).
@@ -44,6 +49,100 @@
             return 1;                                                                  \
         }                                                                              \
     } while (0)
+
+static void write_maps(const std::string &path) {
+    if (path.empty()) return;
+    FILE *in = std::fopen("/proc/self/maps", "r");
+    FILE *out = std::fopen(path.c_str(), "w");
+    if (in && out) {
+        char buf[4096];
+        size_t k;
+        while ((k = std::fread(buf, 1, sizeof(buf), in)) > 0) std::fwrite(buf, 1, k, out);
+    }
+    if (in) std::fclose(in);
+    if (out) std::fclose(out);
+}
+
+// Delaunay mesh refinement of a mesh file, `reps` timed runs (each on a fresh
+// copy of the input) after `warmup` untimed ones.
+static int run_mesh(const char *path, int reps, int warmup, const std::string &maps_out) {
+    FILE *f = std::fopen(path, "rb");
+    char magic[8];
+    int64_t hdr[4];
+    if (!f || std::fread(magic, 1, 8, f) != 8 || std::fread(hdr, 8, 4, f) != 4) {
+        std::fprintf(stderr, "bad mesh file\n");
+        return 1;
+    }
+    const int64_t npts = hdr[0], ntri = hdr[1], pcap = hdr[2], tcap = hdr[3];
+    if (npts < 3 || ntri < 1 || pcap < npts || tcap < ntri || pcap >= (1 << 30) || tcap >= (1 << 30)) {
+        std::fprintf(stderr, "bad mesh sizes\n");
+        return 1;
+    }
+    std::vector<double> pts(static_cast<size_t>(pcap) * 2);
+    std::vector<int32_t> tri(static_cast<size_t>(tcap) * 4), nbr(static_cast<size_t>(tcap) * 4);
+    const bool ok = std::fread(pts.data(), 8, pts.size(), f) == pts.size() &&
+                    std::fread(tri.data(), 4, tri.size(), f) == tri.size() &&
+                    std::fread(nbr.data(), 4, nbr.size(), f) == nbr.size();
+    std::fclose(f);
+    if (!ok) {
+        std::fprintf(stderr, "short mesh file\n");
+        return 1;
+    }
+    double *d_pts;
+    int32_t *d_tri, *d_nbr;
+    CK(hipMalloc(&d_pts, pts.size() * 8));
+    CK(hipMalloc(&d_tri, tri.size() * 4));
+    CK(hipMalloc(&d_nbr, nbr.size() * 4));
+    irgl_mesh m{d_pts, d_tri, d_nbr, static_cast<int32_t>(npts), static_cast<int32_t>(ntri),
+                static_cast<int32_t>(pcap), static_cast<int32_t>(tcap)};
+    size_t wsb = 0;
+    CI(irgl_dmr_workspace_bytes(&m, &wsb));
+    void *ws;
+    CK(hipMalloc(&ws, wsb));
+    irgl_dmr_stats *d_stats;
+    CK(hipMalloc(&d_stats, sizeof(irgl_dmr_stats)));
+    hipStream_t s;
+    CK(hipStreamCreate(&s));
+    hipEvent_t a, b;
+    CK(hipEventCreate(&a));
+    CK(hipEventCreate(&b));
+    double tot_ms = 0;
+    irgl_dmr_stats st{};
+    for (int r = 0; r < warmup + reps; ++r) {
+        CK(hipMemcpy(d_pts, pts.data(), pts.size() * 8, hipMemcpyHostToDevice));
+        CK(hipMemcpy(d_tri, tri.data(), tri.size() * 4, hipMemcpyHostToDevice));
+        CK(hipMemcpy(d_nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice));
+        CK(hipEventRecord(a, s));
+        CI(irgl_dmr_refine(&m, ws, wsb, nullptr, s, d_stats));
+        CK(hipEventRecord(b, s));
+        CK(hipStreamSynchronize(s));
+        CK(hipMemcpy(&st, d_stats, sizeof(st), hipMemcpyDeviceToHost));
+        if (st.status) {
+            std::fprintf(stderr, "dmr: %s\n", irgl_status_string(st.status));
+            return 1;
+        }
+        float ms;
+        CK(hipEventElapsedTime(&ms, a, b));
+        if (r >= warmup) tot_ms += ms;
+    }
+    std::printf("dmr runs=%d mean_ms=%.3f points=%d triangles=%d inserted=%u splits=%u invocations=%u "
+                "rounds=%u conflicts=%llu final_bad=%u grid=%dx%d\n", reps, tot_ms / (reps > 0 ? reps : 1),
+                st.npts, st.ntri, st.inserted, st.splits, st.invocations, st.rounds,
+                static_cast<unsigned long long>(st.conflicts), st.final_bad, st.grid, st.block);
+    CK(hipEventDestroy(a));
+    CK(hipEventDestroy(b));
+    CK(hipStreamDestroy(s));
+    CK(hipFree(d_stats));
+    CK(hipFree(ws));
+    CK(hipFree(d_pts));
+    CK(hipFree(d_tri));
+    CK(hipFree(d_nbr));
+    CI(irgl_shutdown());
+    write_maps(maps_out);
+    std::printf("runner done\n");
+    std::fflush(stdout);
+    return 0;
+}
 
 int main(int argc, char **argv) {
     if (argc < 2) {
@@ -79,6 +178,14 @@ int main(int argc, char **argv) {
             std::fprintf(stderr, "unknown option %s\n", k.c_str());
             return 2;
         }
+    }
+    {
+        // a mesh file (meshgen.py): Delaunay refinement instead of queries
+        FILE *mf = std::fopen(argv[1], "rb");
+        char mg[8] = {0};
+        const bool is_mesh = mf && std::fread(mg, 1, 8, mf) == 8 && std::memcmp(mg, "IRGLMSH1", 8) == 0;
+        if (mf) std::fclose(mf);
+        if (is_mesh) return run_mesh(argv[1], reps, warmup, maps_out);
     }
     FILE *f = std::fopen(argv[1], "rb");
     if (!f) {
@@ -233,17 +340,7 @@ int main(int argc, char **argv) {
     CK(hipFree(d_out));
     if (d_w) CK(hipFree(d_w));
     CI(irgl_shutdown());
-    if (!maps_out.empty()) {
-        FILE *in = std::fopen("/proc/self/maps", "r");
-        FILE *out = std::fopen(maps_out.c_str(), "w");
-        if (in && out) {
-            char buf[4096];
-            size_t k;
-            while ((k = std::fread(buf, 1, sizeof(buf), in)) > 0) std::fwrite(buf, 1, k, out);
-        }
-        if (in) std::fclose(in);
-        if (out) std::fclose(out);
-    }
+    write_maps(maps_out);
     std::printf("runner done\n");
     std::fflush(stdout);
     return 0;

@@ -82,3 +82,36 @@ def random_square(npoints: int, seed: int, k: int = 0, tri_factor: float = 8.0, 
     nbr = np.full((tcap, 4), -1, dtype=np.int32)
     nbr[:T, :3] = nb
     return Mesh(P, tri, nbr, pts.shape[0], T, f"square_n{npoints}_k{k}_s{seed}")
+
+
+MAGIC = b"IRGLMSH1"
+
+
+def write_mesh(path: str, m: Mesh) -> None:
+    """Binary mesh file for the native runner (little endian): b"IRGLMSH1",
+    int64 npts, ntri, pcap, tcap, float64 pts[pcap][2], int32 tri[tcap][4],
+    int32 nbr[tcap][4]."""
+    with open(path, "wb") as f:
+        f.write(MAGIC)
+        f.write(np.array([m.npts, m.ntri, m.pts.shape[0], m.tri.shape[0]], dtype=np.int64).tobytes())
+        f.write(np.ascontiguousarray(m.pts, dtype=np.float64).tobytes())
+        f.write(np.ascontiguousarray(m.tri, dtype=np.int32).tobytes())
+        f.write(np.ascontiguousarray(m.nbr, dtype=np.int32).tobytes())
+
+
+def main(argv=None) -> int:
+    import argparse
+    ap = argparse.ArgumentParser(description="write a random-square mesh as a binary file")
+    ap.add_argument("out")
+    ap.add_argument("--points", type=int, default=1000000)
+    ap.add_argument("--seed", type=int, default=42)
+    args = ap.parse_args(argv)
+    m = random_square(args.points, args.seed)
+    write_mesh(args.out, m)
+    print(f"wrote {args.out}: {m.name} points={m.npts} triangles={m.ntri}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

@@ -402,9 +402,10 @@ def test_watchdog_and_abort_forced_from_host(irgl):
     _check_query(irgl, g, hg, BFS, 0, {"abort_flag": flag.data_ptr()})
 
 
-def _expected_default_delta(g, validated=True):
+def _expected_default_delta(g, validated=True, partitioned=False):
     """The default near/far step written out from the graph's shape: mean
-    weight W, mean out-degree D, largest out-degree X (host arrays)."""
+    weight W, mean out-degree D, largest out-degree X (host arrays);
+    `partitioned`: a relabelled weighted upload (light/heavy SSSP copy)."""
     rp, col, w = g.numpy()
     if not validated or w is None or g.m == 0:
         return 0xFFFFFFFF
@@ -415,7 +416,11 @@ def _expected_default_delta(g, validated=True):
         d = 32.0 * mean_w / max(1.0, mean_deg)
     elif x <= 16.0 * mean_deg:
         d = 16.0 * mean_w / mean_deg
-    elif g.m >= 1 << 26:
+    elif partitioned and g.m >= 1 << 25:
+        d = mean_w / 4.0
+    elif partitioned and g.m >= 1 << 24:
+        d = mean_w / 2.0
+    elif not partitioned and g.m >= 1 << 26:
         d = mean_w
     else:
         return 0xFFFFFFFF
@@ -426,18 +431,19 @@ def test_default_near_far_step(irgl):
     cases = [
         (gg.uniform_random(1 << 14, 16.0, seed=61, weight_seed=62, wmax=1000), "near-regular, D 16"),
         (gg.uniform_random(1 << 14, 32.0, seed=63, weight_seed=64, wmax=1000), "near-regular, D 32"),
-        (gg.rmat(14, seed=65, weight_seed=66, wmax=255), "scale-free, below 2^26 edges"),
+        (gg.rmat(14, seed=65, weight_seed=66, wmax=255), "scale-free, below 2^24 edges"),
+        (gg.rmat(20, seed=70, weight_seed=71, wmax=255), "scale-free, 2^24 to 2^25 edges"),
         (gg.config_road(width=64), "road-like, D < 8"),
         (gg.rmat(12, seed=67), "unweighted"),
     ]
     seen = set()
     for g, what in cases:
         g = _dev(g)
-        want = _expected_default_delta(g)
-        _say(f"default near/far step: {what} ({g.name}) -> {want}")
         for reorder in (False, True):
+            want = _expected_default_delta(g, partitioned=reorder and g.w is not None)
+            _say(f"default near/far step: {what} ({g.name}), relabelled={reorder} -> {want}")
             assert irgl.irgl_graph_default_delta(irgl.upload(g, reorder=reorder)) == want, (what, reorder)
-        seen.add(want == 0xFFFFFFFF)
+            seen.add(want == 0xFFFFFFFF)
         if g.w is not None:
             src = g.sources[0] if g.sources else 0
             _check_query(irgl, g, irgl.upload(g), SSSP, src, with_parent=False)
