@@ -109,6 +109,7 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.m = 0;
     p.reduce_all = 0;
     p.tail_div = 0;  // without the split the bucketing runs to its end
+    p.shadow16 = 0;
     return p;
 }
 

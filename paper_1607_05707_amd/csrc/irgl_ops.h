@@ -96,6 +96,10 @@ struct Params {
     // bucketing (threshold = INF: the rest runs in plain Bellman-Ford order);
     // 0 = never
     uint32_t tail_div;
+    // SSSP: the shadow distances are 16-bit (saturating at 0xFFFF = "no
+    // bound"), half the probe footprint; for graphs whose distances are
+    // small (the split scale-free path)
+    uint32_t shadow16;
 };
 
 // ---------------------------------------------------------------------------
@@ -179,6 +183,9 @@ struct SsspOp {
     // its lines stay cacheable in L2 while dist's lines, hammered by atomics,
     // do not.  A relaxation that cannot beat the bound cannot improve dist.
     uint32_t *shadow;
+    // 1: shadow holds 16-bit values, min(bound, 0xFFFF); 0xFFFF reads as no
+    // bound, so a saturated entry only weakens the filter
+    uint32_t shadow16 = 0;
     // Light/heavy split (null: every edge is relaxed when its source is
     // expanded).  Rows are partitioned so that edges lighter than the step
     // come first; an expansion relaxes only [row_ptr[v], split[v]) and lists
@@ -218,14 +225,24 @@ struct SsspOp {
         }
         if (ovf) set_error(ctrl, kErrOverflow, false);
 #pragma unroll
-        for (int k = 0; k < kU; ++k) cur[k] = act[k] ? shadow[d[k]] : 0u;
+        for (int k = 0; k < kU; ++k) {
+            if (shadow16) {  // uniform
+                const uint32_t h = act[k] ? reinterpret_cast<const uint16_t *>(shadow)[d[k]] : 0u;
+                cur[k] = h == 0xFFFFu ? kInf : h;
+            } else {
+                cur[k] = act[k] ? shadow[d[k]] : 0u;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {
             act[k] = act[k] && nd[k] < cur[k];
             tries += act[k] ? 1u : 0u;
             if (act[k]) act[k] = nd[k] < atomicMin(&dist[d[k]], nd[k]);
             wins += act[k] ? 1u : 0u;
-            if (act[k]) shadow[d[k]] = nd[k];
+            if (act[k]) {
+                if (shadow16) reinterpret_cast<uint16_t *>(shadow)[d[k]] = static_cast<uint16_t>(min(nd[k], 0xFFFFu));
+                else shadow[d[k]] = nd[k];
+            }
         }
 #pragma unroll
         for (int k = 0; k < kU; ++k) {

@@ -22,7 +22,8 @@ __device__ __forceinline__ void init_arrays(const Params &p, int with_stamp, Tea
         if (p.parent) p.parent[i] = s ? p.src_orig : -1;
         if (with_stamp) {
             p.stamp[i] = kInf;
-            p.shadow[i] = s ? 0u : kInf;
+            if (p.shadow16) reinterpret_cast<uint16_t *>(p.shadow)[i] = s ? 0 : 0xFFFF;
+            else p.shadow[i] = s ? 0u : kInf;
             p.far_flag[i] = 0u;
             if (p.expd) p.expd[i] = kInf;
             if (p.hstamp) p.hstamp[i] = kInf;
@@ -81,6 +82,7 @@ template <>
 __device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, uint32_t thresh, uint32_t bucket,
                                                   bool heavy) {
     SsspOp op{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited, p.shadow};
+    op.shadow16 = p.shadow16;
     op.split = p.split;
     op.expd = heavy ? nullptr : p.expd;
     op.hstamp = (heavy || !p.split) ? nullptr : p.hstamp;
