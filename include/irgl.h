@@ -64,7 +64,11 @@ enum {
 enum { IRGL_KIND_BFS = 0, IRGL_KIND_SSSP = 1 };
 
 /* Graph flags. */
-#define IRGL_SYMMETRIC 1u /* informational: every edge has its reverse with equal weight */
+/* The caller's promise (not checked) that every edge has its reverse with
+ * equal weight: BFS may then run bottom-up invocations and SSSP on a split
+ * graph may run a heavy pass as a pull, both of which read a vertex's
+ * out-edges as its in-edges. */
+#define IRGL_SYMMETRIC 1u
 #define IRGL_VALIDATE 2u  /* check the CSR on the device during upload (synchronizes) */
 
 #define IRGL_WATCHDOG_IMMEDIATE 0xFFFFFFFFu
@@ -210,7 +214,9 @@ typedef struct irgl_stats {
     uint32_t max_frontier; /* largest incoming worklist */
     int32_t grid;          /* workgroups used */
     int32_t block;         /* threads per workgroup used */
-    uint32_t reserved;
+    uint32_t heavy_pulls;  /* SSSP heavy passes run as a pull (Section 4.1's
+                              heavy edges seen from their unsettled ends, on a
+                              split symmetric graph); 0 for BFS and batches */
     uint64_t frontier_edges; /* sum of the out-degrees of every worklist (BFS: the
                              CSR entries an exact top-down traversal scans, also
                              when bottom-up invocations scanned fewer) */

@@ -85,6 +85,7 @@ struct irgl_graph_s {
     int32_t *split_store = nullptr;
     const int32_t *split = nullptr;
     uint32_t split_delta = IRGL_DELTA_NONE;
+    unsigned long long heavy_m = 0;  // heavy entries of the partition
     // SSSP near/far step of single queries that leave it at 0
     uint32_t qdelta = IRGL_DELTA_NONE;
 };
@@ -140,6 +141,11 @@ uint32_t delta_rule(const irgl_graph_s *g, bool partitioned);
 bool scale_free(const irgl_graph_s *g);
 // Far-list divisor of the bucketing's early end on split scale-free graphs.
 constexpr uint32_t kTailDiv = 16;
+// A bucket whose listed vertices hold at least n / kPullHeavyDiv heavy edges,
+// and at least 1 / kPullOpenDiv of the heavy edges of the vertices not yet
+// listed, runs its heavy pass as a pull.
+constexpr uint32_t kPullHeavyDiv = 2;
+constexpr uint32_t kPullOpenDiv = 2;
 // Step of the light/heavy partition on a scale-free graph, as a fraction of
 // the mean weight W: each heavy edge is then relaxed once, while a smaller
 // step adds buckets (one barrier each).  Measured on R-MAT graphs of scales
@@ -537,6 +543,13 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
         if (scale_free(g)) {
             p.tail_div = kTailDiv;
             p.shadow16 = 1;
+        }
+        // the pull form of the heavy pass reads a vertex's heavy range as the
+        // heavy edges INTO it: symmetric graphs only
+        if (g->flags & IRGL_SYMMETRIC) {
+            p.pull_heavy_div = kPullHeavyDiv;
+            p.pull_open_div = kPullOpenDiv;
+            p.heavy_m = g->heavy_m;
         }
     }
     p.val = g->perm ? reinterpret_cast<uint32_t *>(base + L.rval) : out;
@@ -939,6 +952,7 @@ __global__ void partition_rows_kernel(int32_t n, const int32_t *rp, const int32_
 irgl_status build_partition(irgl_graph_s *g, uint32_t delta) {
     g->split = nullptr;
     g->split_delta = IRGL_DELTA_NONE;
+    g->heavy_m = 0;
     if (!g->scol || delta == IRGL_DELTA_NONE || g->m == 0) return IRGL_OK;
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, 0);
     IRGL_HIP(hipGetLastError());
@@ -952,6 +966,7 @@ irgl_status build_partition(irgl_graph_s *g, uint32_t delta) {
     IRGL_HIP(hipMemcpy(&h, heavy, 8, hipMemcpyDeviceToHost));
     g->split = h ? g->split_store : nullptr;
     g->split_delta = delta;
+    g->heavy_m = h;
     return IRGL_OK;
 }
 
@@ -1367,7 +1382,7 @@ irgl_status irgl_query_status(const void *ws, void *stream, irgl_stats *out) {
     out->max_frontier = c.max_frontier;
     out->grid = c.grid;
     out->block = c.block;
-    out->reserved = 0;
+    out->heavy_pulls = c.pulls;
     out->frontier_edges = c.fedges;
     return IRGL_OK;
 }

@@ -110,6 +110,9 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.reduce_all = 0;
     p.tail_div = 0;  // without the split the bucketing runs to its end
     p.shadow16 = 0;
+    p.pull_heavy_div = 0;
+    p.pull_open_div = 0;
+    p.heavy_m = 0;
     return p;
 }
 
@@ -125,7 +128,7 @@ __device__ __forceinline__ void write_task_stats(const Params &p, const LoopResu
     s->max_frontier = r.max_frontier;
     s->grid = static_cast<int32_t>(tm.size);
     s->block = block;
-    s->reserved = 0;
+    s->heavy_pulls = 0;
     s->frontier_edges = __hip_atomic_load(&p.ctrl->fedges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -287,7 +290,7 @@ __device__ __forceinline__ void report_task(const ServerParams &sp, const TaskDe
     hs->max_frontier = ds->max_frontier;
     hs->grid = ds->grid;
     hs->block = ds->block;
-    hs->reserved = 0;
+    hs->heavy_pulls = 0;
     hs->frontier_edges = ds->frontier_edges;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     __hip_atomic_store(&sp.done[slot], ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -70,9 +70,18 @@ struct alignas(128) Ctrl {
     int32_t grid;
     int32_t block;
     unsigned long long fedges;  // sum of out-degrees of every frontier
+    // rotating SSSP sums of the heavy out-degrees of the listed vertices
+    // (indexed by threshold raises so far): the edges a push heavy pass scans
+    unsigned long long hsum[3];
     // rotating SSSP heavy-list counters (indexed by threshold raises so far)
     uint32_t hcnt[3];
-    uint32_t pad4[19];
+    // rotating SSSP smallest distance of a vertex expanded in the bucket
+    uint32_t hmin[3];
+    // rotating (per invocation) SSSP flag: a pull heavy pass met a vertex it
+    // leaves to the push pass
+    uint32_t hbig[3];
+    uint32_t pulls;  // SSSP heavy passes run as a pull
+    uint32_t pad4[6];
 };
 static_assert(sizeof(Ctrl) == 13 * 128, "control block layout");
 
@@ -85,7 +94,7 @@ struct Stats {
     uint32_t max_frontier;
     int32_t grid;
     int32_t block;
-    uint32_t reserved;
+    uint32_t heavy_pulls;
     unsigned long long frontier_edges;
 };
 

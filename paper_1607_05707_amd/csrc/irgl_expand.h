@@ -31,6 +31,10 @@ struct Pushers {
     uint32_t wins = 0;        // ... and the successful ones
     WaveQueue<kHeavyQ> hq{nullptr, 0};  // SSSP heavy list of the current bucket
     Sink skh{};               // its sink (cnt_out null: no heavy list in this invocation)
+    unsigned long long hdeg = 0;           // this lane's heavy out-degrees of listed vertices
+    unsigned long long *hsum_out = nullptr;  // ... drained into this per-bucket counter
+    uint32_t hminv = kInf;                 // this lane's smallest distance of an expanded vertex
+    uint32_t *hmin_out = nullptr;          // ... drained into this per-bucket minimum
     __device__ __forceinline__ void near(bool p, int item) {
         nq.push(p, item, sk.cnt_out, sk.out, sk.cap, sk.ctrl);
     }
@@ -86,6 +90,17 @@ __device__ __forceinline__ bool op_pop<SsspOp>(const SsspOp &op, int v, uint32_t
     return true;
 }
 
+// Heavy out-degree of vertex v (the part of its row a heavy pass scans).
+template <class Op>
+__device__ __forceinline__ unsigned long long op_heavy_degree(const Op &, const int32_t *__restrict__, int) {
+    return 0ull;
+}
+template <>
+__device__ __forceinline__ unsigned long long op_heavy_degree<SsspOp>(const SsspOp &op, const int32_t *__restrict__ rp,
+                                                                       int v) {
+    return op.split ? static_cast<unsigned long long>(rp[v + 1] - op.split[v]) : 0ull;
+}
+
 // Workgroup-wide drain of both queues (all threads call it).
 template <int B, class Op, class S>
 __device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
@@ -100,6 +115,21 @@ __device__ __forceinline__ void drain_all(Pushers &pu, S &sm) {
     }
     if (Op::kFar && pu.skh.cnt_out)  // uniform: the same sink for the whole team
         block_drain<B, kHeavyQ>(pu.hq, sm.fill, &sm.base, pu.skh.cnt_out, pu.skh.out, pu.skh.cap, pu.skh.ctrl);
+    if (Op::kFar && pu.hsum_out) {  // uniform; one atomicAdd and one atomicMin per wavefront
+        unsigned long long x = pu.hdeg;
+        uint32_t mn = pu.hminv;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            x += __shfl_xor(x, d, kWave);
+            mn = min(mn, static_cast<uint32_t>(__shfl_xor(mn, d, kWave)));
+        }
+        if (lane_id() == 0 && x) atomicAdd(pu.hsum_out, x);
+        if (lane_id() == 0 && mn != kInf) atomicMin(pu.hmin_out, mn);
+    }
+    // also where nothing was drained (a heavy pass expands settled vertices):
+    // their values must not reach the next bucket's minimum
+    pu.hdeg = 0;
+    pu.hminv = kInf;
     if (Op::kFar) {
         block_drain<B, kQueueCap>(pu.fq, sm.fill, &sm.base, pu.skf.cnt_out, pu.skf.out, pu.skf.cap,
                                   pu.skf.ctrl);
@@ -213,9 +243,14 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
             return;
         }
         val = op.vertex_value(v);
-        bool hp = false;
-        if (op.active(val) && op_pop(op, v, val, hp)) op_range(op, row_ptr, v, r0, r1);
+        bool hp = false, ex = false;
+        if (op.active(val) && op_pop(op, v, val, hp)) {
+            op_range(op, row_ptr, v, r0, r1);
+            ex = true;
+        }
         pu.heavy(hp && lane == 0, v);
+        if (hp && lane == 0) pu.hdeg += op_heavy_degree(op, row_ptr, v);
+        if (ex) pu.hminv = min(pu.hminv, val);  // every expansion, listed or not
         const int deg = r1 - r0;
         if (lane == 0) edges += static_cast<unsigned long long>(deg);
         if (deg >= B) {  // a range of a whole round or more goes to the grid tier
@@ -249,7 +284,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         const uint32_t i = base + tid;
         int v = -1, r0 = 0, r1 = 0;
         uint32_t val = 0;
-        bool hp = false;
+        bool hp = false, ex = false;
         if (i < cnt_in) {
             v = in ? in[i] : static_cast<int>(i);
             if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
@@ -257,10 +292,15 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
                 v = -1;
             } else {
                 val = op.vertex_value(v);
-                if (op.active(val) && op_pop(op, v, val, hp)) op_range(op, row_ptr, v, r0, r1);
+                if (op.active(val) && op_pop(op, v, val, hp)) {
+                    op_range(op, row_ptr, v, r0, r1);
+                    ex = true;
+                }
             }
         }
         pu.heavy(hp, v);
+        if (hp) pu.hdeg += op_heavy_degree(op, row_ptr, v);
+        if (ex) pu.hminv = min(pu.hminv, val);  // every expansion, listed or not
         int deg = r1 - r0;
         edges += static_cast<unsigned long long>(deg);
 

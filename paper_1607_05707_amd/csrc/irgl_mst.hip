@@ -507,7 +507,7 @@ __global__ __launch_bounds__(B) void mst_kernel(MstParams p) {
             s->max_frontier = 0;
             s->grid = static_cast<int32_t>(tm.size);
             s->block = B;
-            s->reserved = 0;
+            s->heavy_pulls = 0;
             s->frontier_edges = __hip_atomic_load(forest_count(ctrl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }

@@ -100,6 +100,16 @@ struct Params {
     // bound"), half the probe footprint; for graphs whose distances are
     // small (the split scale-free path)
     uint32_t shadow16;
+    // SSSP on a split symmetric graph: a bucket whose listed vertices hold at
+    // least n / pull_heavy_div heavy edges runs its heavy pass as a pull
+    // (every unsettled vertex looks through its own heavy range for the
+    // bucket's vertices); 0 = always push
+    uint32_t pull_heavy_div;
+    // ... and whose listed heavy edges are at least 1 / pull_open_div of the
+    // heavy edges of the vertices not listed before (the pull scans those);
+    // 0 = no such bound.  heavy_m = heavy edges of the partition.
+    uint32_t pull_open_div;
+    unsigned long long heavy_m;
 };
 
 // ---------------------------------------------------------------------------
@@ -153,6 +163,22 @@ struct BfsOp {
         }
     }
 };
+
+// The register cap of a persistent kernel of B threads per workgroup: the
+// fewest waves per SIMD that hold as many whole workgroups per compute unit
+// (four SIMDs) as a cap of W waves per SIMD would.  Where W waves do not
+// divide into whole workgroups (two workgroups of 512 threads fill 4 of 5),
+// the looser cap gives the compiler more registers, hence fewer spills, for
+// the same co-resident grid.
+template <int B, int W>
+constexpr int fit_waves() {
+    constexpr int per_block = B / kWave;
+    constexpr int blocks = (4 * W) / per_block;
+    return blocks <= 0 ? W : (blocks * per_block + 3) / 4;
+}
+static_assert(fit_waves<256, 5>() == 5 && fit_waves<512, 5>() == 4 && fit_waves<1024, 5>() == 4 &&
+                  fit_waves<512, 1>() == 1,
+              "register cap per workgroup size");
 
 // SSSP relaxation with a near/far split of the worklist (a bucketed,
 // delta-stepping order of the same data-driven loop): an improved vertex

@@ -588,7 +588,7 @@ __global__ __launch_bounds__(B) void pipe_kernel(Params p) {
             st->max_frontier = s.max_in;
             st->grid = static_cast<int32_t>(tm.size);
             st->block = B;
-            st->reserved = 0;
+            st->heavy_pulls = 0;
             st->frontier_edges = 0;
         }
     }

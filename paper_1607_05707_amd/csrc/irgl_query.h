@@ -49,6 +49,9 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
             c->far_cnt[k] = 0;
             c->far_min[k] = kInf;
             c->hcnt[k] = 0;
+            c->hsum[k] = 0;
+            c->hmin[k] = kInf;
+            c->hbig[k] = 0;
         }
         if (reset_barrier) reset_barrier_words(c);
         c->error = 0;
@@ -59,6 +62,7 @@ __device__ __forceinline__ void init_control(const Params &p, bool reset_barrier
         c->items = 0;
         c->edges = 0;
         c->fedges = 0;
+        c->pulls = 0;
         c->mf[0] = static_cast<unsigned long long>(p.row_ptr[p.src + 1] - p.row_ptr[p.src]);
         c->mf[1] = 0;
         c->mf[2] = 0;
@@ -130,7 +134,7 @@ __device__ __forceinline__ void publish_stats(const Params &p) {
     s->max_frontier = c->max_frontier;
     s->grid = c->grid;
     s->block = c->block;
-    s->reserved = 0;
+    s->heavy_pulls = c->pulls;
     s->frontier_edges = __hip_atomic_load(&c->fedges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -332,6 +336,76 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
 }
 
 // ---------------------------------------------------------------------------
+// SSSP heavy pass as a pull (split symmetric graphs): every vertex u whose
+// distance exceeds `lo` scans its heavy range for vertices listed in bucket
+// `bucket` (their distances are final) and takes the smallest
+// dist[v] + w(v, u) through the operator's relaxation, as if that one edge
+// had been pushed.  Each u is decided by one lane.  `lo` is the smallest
+// distance any vertex was expanded with in the bucket plus the step (a
+// listed vertex's final distance is the one of its last expansion): a heavy
+// edge (weight at least the step) from the bucket cannot bring any vertex to
+// `lo` or below, so those vertices are skipped whatever the bucket's width.  (The threshold
+// itself is no bound: it jumps over empty ranges, so a bucket can be wider
+// than the step and vertices below it can still improve.)
+// ---------------------------------------------------------------------------
+// A vertex whose heavy range is longer than this is not scanned by one lane:
+// it raises *big, and the caller runs the push pass after all.
+constexpr int kPullMaxRange = 1024;
+
+template <int B, class Op>
+__device__ __forceinline__ void pull_heavy(const Params &p, const Op &hop, uint32_t lo, uint32_t bucket, Team tm,
+                                           Pushers &pu, unsigned long long &scanned, uint32_t *big) {
+    const uint32_t n = static_cast<uint32_t>(p.n);
+    bool saw_big = false;
+    for (uint32_t base = tm.id * B; base < n; base += tm.size * B) {
+        const uint32_t u = base + threadIdx.x;
+        int e[Op::kU], d[Op::kU], sv[Op::kU];
+        uint32_t dv[Op::kU];
+        bool act[Op::kU], far[Op::kU];
+#pragma unroll
+        for (int k = 0; k < Op::kU; ++k) {
+            e[k] = 0;
+            d[k] = 0;
+            sv[k] = 0;
+            dv[k] = 0;
+            act[k] = false;
+            far[k] = false;
+        }
+        if (u < n && p.val[u] > lo) {
+            const uint32_t du = p.val[u];
+            const int r0 = p.split[u];
+            int r1 = p.row_ptr[u + 1];
+            if (r1 - r0 > kPullMaxRange) {
+                saw_big = true;
+                r1 = r0;
+            }
+            unsigned long long best = du;
+            for (int x = r0; x < r1; ++x) {
+                const int v = p.col[x];
+                if (p.hstamp[v] != bucket) continue;
+                const unsigned long long c =
+                    static_cast<unsigned long long>(p.val[v]) + static_cast<unsigned long long>(p.w[x]);
+                if (c < best) {
+                    best = c;
+                    e[0] = x;
+                    sv[0] = v;
+                    dv[0] = p.val[v];
+                    act[0] = true;
+                }
+            }
+            d[0] = static_cast<int>(u);
+            scanned += static_cast<unsigned long long>(r1 - r0);
+        }
+        hop.relax(e, d, sv, dv, act, far, pu.fmin, pu.tries, pu.wins);
+#pragma unroll
+        for (int k = 0; k < Op::kU; ++k) pu.near(act[k], d[k]);
+#pragma unroll
+        for (int k = 0; k < Op::kU; ++k) pu.far(far[k], d[k]);
+    }
+    if (__syncthreads_or(saw_big) && threadIdx.x == 0) atomicOr(big, 1u);
+}
+
+// ---------------------------------------------------------------------------
 // The outlined Iterate loop, run by one team (the whole grid of a
 // single-query launch, or one group of a batched launch).  An invocation that
 // deferred vertices to the grid tier has two team barriers (after phase A,
@@ -346,6 +420,7 @@ struct LoopResult {
     unsigned long long edges;   // CSR entries this workgroup scanned
     uint32_t max_frontier;
     unsigned long long fedges;  // out-degree sums of the worklists (this workgroup's share)
+    uint32_t pulls;             // SSSP heavy passes run as a pull (uniform)
 };
 
 template <int B, class Op>
@@ -359,7 +434,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     // vertex for its bucket's heavy pass, which runs in the bucket's transfer
     // invocation (one barrier for both)
     const bool split = Op::kFar && p.split != nullptr;
-    LoopResult r{0u, 0ull, 0ull, 0u, 0ull};
+    LoopResult r{0u, 0ull, 0ull, 0u, 0ull, 0u};
     // BFS direction choice (needs the frontier bitmap; symmetric graphs only)
     bool can_pull = !Op::kFar && p.frontier != nullptr;
     bool pull = false;
@@ -378,6 +453,7 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
     // popped items when the bitmap was last refreshed: refresh again once the
     // newly reached vertices carry enough edges to repay a full scan
     unsigned long long refreshed = 0;
+    unsigned long long hdone = 0;  // heavy edges of the buckets drained so far
 
     for (;; ++it) {
         uint32_t cnt_in = load_agent(&ctrl->cnt[it % 3]);
@@ -400,10 +476,14 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             store_agent(&ctrl->tile[(it + 2) % 3], 0u);
             __hip_atomic_store(&ctrl->hub[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctrl->mf[(it + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // read inside invocation it after a barrier of it: clear the next one's
+            store_agent(&ctrl->hbig[(it + 1) % 3], 0u);
             if (cnt_in == 0) {
                 store_agent(&ctrl->far_cnt[(tr + 2) % 3], 0u);
                 store_agent(&ctrl->far_min[(tr + 2) % 3], kInf);
                 store_agent(&ctrl->hcnt[(tr + 1) % 3], 0u);  // the next bucket's heavy list
+                __hip_atomic_store(&ctrl->hsum[(tr + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                store_agent(&ctrl->hmin[(tr + 1) % 3], kInf);
             }
             if (tracing(p, it)) trace_start(p, it, cnt_in);
         }
@@ -428,31 +508,61 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             }
             pu.skf = far_sink(p, tr + 1);
             pu.skh = Sink{};
+            pu.hsum_out = nullptr;
             far_transfer<B>((tr & 1u) ? p.far1 : p.far0, far_n, static_cast<uint32_t>(p.n), thresh, t_new,
                             p.val, p.far_flag, p.stamp, it, pu, tm);
             // heavy pass of the drained bucket (split graphs): its vertices'
             // distances are final, so each heavy edge is relaxed once; the
             // results (at least thresh) go to the next worklist (below t_new)
-            // or the far list
+            // or the far list.  Push: the listed vertices' heavy ranges.
+            // Pull, when those ranges are many: each unsettled vertex scans
+            // its own heavy range for the bucket's vertices (the same edges
+            // seen from the other end of a symmetric graph).
             const unsigned long long edges_before = r.edges;
             const Op hop = make_op<Op>(p, it, t_new, tr, true);
-            if (nheavy > 0)
-                expand<B, Op>(p.hlist, nheavy, static_cast<uint32_t>(p.n), p.row_ptr, p.col, hop, sm, pu, p.t_wave,
-                              p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm,
-                              &ctrl->tile[it % 3]);
-            drain_all<B, Op>(pu, sm);
-            if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
-            if (nheavy > 0 && p.t_grid > 0) {
-                uint32_t nh, nchunks;
-                hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
-                           nh, nchunks);
-                if (nh > 0) {
-                    expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, hop, sm, pu, tm);
-                    drain_all<B, Op>(pu, sm);
-                    if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+            // Pull only for a bucket no wider than the step (the smallest
+            // expanded distance plus the step reaches the drained threshold):
+            // then the vertices it scans are those beyond the threshold.
+            const uint32_t hm = load_agent(&ctrl->hmin[tr % 3]);
+            const uint32_t lo = hm >= kInf - p.delta ? kInf : hm + p.delta;
+            const unsigned long long hs =
+                p.pull_heavy_div ? __hip_atomic_load(&ctrl->hsum[tr % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0ull;
+            const unsigned long long open = p.heavy_m > hdone ? p.heavy_m - hdone : 0ull;
+            hdone += hs;
+            bool pull_h = nheavy > 0 && p.pull_heavy_div && lo >= thresh &&
+                          hs * p.pull_heavy_div >= static_cast<unsigned long long>(p.n) &&
+                          (p.pull_open_div == 0 || hs * p.pull_open_div >= open);
+            bool pulled = false;
+            if (pull_h) {
+                if constexpr (Op::kFar) pull_heavy<B, Op>(p, hop, lo, tr, tm, pu, r.edges, &ctrl->hbig[it % 3]);
+                drain_all<B, Op>(pu, sm);
+                if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+                // an unsettled vertex with a long heavy range was left out: the
+                // push pass relaxes every listed vertex's heavy edges after all
+                // (the pull's relaxations were real edges: nothing to undo)
+                pulled = load_agent(&ctrl->hbig[it % 3]) == 0u;
+                r.pulls += pulled ? 1u : 0u;
+            }
+            if (!pulled) {
+                if (nheavy > 0)
+                    expand<B, Op>(p.hlist, nheavy, static_cast<uint32_t>(p.n), p.row_ptr, p.col, hop, sm, pu,
+                                  p.t_wave, p.t_block, p.t_grid, p.hub_v, p.hub_base, p.hub_cap, hub_ctr, r.edges, tm,
+                                  &ctrl->tile[it % 3]);
+                drain_all<B, Op>(pu, sm);
+                if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+                if (nheavy > 0 && p.t_grid > 0) {
+                    uint32_t nh, nchunks;
+                    hub_counts(__hip_atomic_load(hub_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), p.hub_cap,
+                               nh, nchunks);
+                    if (nh > 0) {
+                        expand_hubs<B, Op>(nh, nchunks, p.hub_v, p.hub_base, p.row_ptr, p.col, hop, sm, pu, tm);
+                        drain_all<B, Op>(pu, sm);
+                        if (!grid_barrier(ctrl, bs, &sm.flag, p.abort_flag, tm)) break;
+                    }
                 }
             }
-            if (nheavy > 0 && tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
+            if ((nheavy > 0 || pulled) && tracing(p, it)) trace_level(p, it, r.edges - edges_before, hub_ctr, tm, pu);
             thresh = t_new;
             ++tr;
         } else if (can_pull && ([&] {
@@ -498,6 +608,8 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             bitmaps_current = false;  // top-down labels are not in the bitmaps
             pu.skf = far_sink(p, tr);
             pu.skh = split ? Sink{&ctrl->hcnt[tr % 3], p.hlist, p.hcap, ctrl, nullptr} : Sink{};
+            pu.hsum_out = (split && p.pull_heavy_div) ? &ctrl->hsum[tr % 3] : nullptr;
+            pu.hmin_out = &ctrl->hmin[tr % 3];
             pu.mf_out = &ctrl->mf[(it + 1) % 3];
             const unsigned long long edges_before = r.edges;
             if (!Op::kFar && p.visited && r.items - refreshed >= p.t_bitmap) {
@@ -550,6 +662,7 @@ __device__ __forceinline__ void finish_query(const Params &p, const LoopResult &
             ctrl->iterations = r.iterations;
             ctrl->items = r.items;
             ctrl->max_frontier = r.max_frontier;
+            ctrl->pulls = r.pulls;
             ctrl->grid = static_cast<int32_t>(tm.size);
             ctrl->block = B;
         }
@@ -576,7 +689,7 @@ __device__ __forceinline__ void map_to_caller(const Params &p, Team tm) {
 
 // One query per cooperative launch: the whole grid is the team.
 template <int B, class Op>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(Op::kMinWaves))) void persistent_kernel(
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(fit_waves<B, Op::kMinWaves>()))) void persistent_kernel(
     Params p) {
     __shared__ Smem<B> sm;
     const Team tm = whole_grid();

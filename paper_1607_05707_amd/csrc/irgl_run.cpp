@@ -303,7 +303,7 @@ int main(int argc, char **argv) {
         irgl_stats st;
         CI(irgl_query_status(ws, s, &st));
         // work of one more (untimed) pass: CSR entries scanned per reached edge
-        double scanned = 0;
+        double scanned = 0, pulls = 0;
         for (int i = 0; i < nsrc; ++i) {
             CI(run(src[i]));
             irgl_stats sq;
@@ -313,6 +313,7 @@ int main(int argc, char **argv) {
                 return 1;
             }
             scanned += static_cast<double>(sq.edges);
+            pulls += sq.heavy_pulls;
         }
         double mcc_sum = 0;
         for (int i = 0; i < nsrc; ++i) mcc_sum += static_cast<double>(mcc[i]);
@@ -324,9 +325,9 @@ int main(int argc, char **argv) {
             edges += static_cast<double>(mcc[q % nsrc]);
         }
         std::printf("%s queries=%d mean_us=%.1f gteps=%.3f status=%d iterations=%u grid=%dx%d "
-                    "scans_per_edge=%.3f\n", name, nsrc * reps, 1e3 * tot_ms / (nsrc * reps),
+                    "scans_per_edge=%.3f heavy_pulls=%.2f\n", name, nsrc * reps, 1e3 * tot_ms / (nsrc * reps),
                     edges / (tot_ms * 1e-3) / 1e9, st.status, st.iterations, st.grid, st.block,
-                    mcc_sum > 0 ? scanned / mcc_sum : 0.0);
+                    mcc_sum > 0 ? scanned / mcc_sum : 0.0, nsrc > 0 ? pulls / nsrc : 0.0);
         std::fflush(stdout);
         for (auto &e : ev) CK(hipEventDestroy(e));
         CK(hipFree(ws));

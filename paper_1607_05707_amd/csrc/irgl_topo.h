@@ -134,7 +134,7 @@ __device__ __forceinline__ LoopResult run_topology(const Params &p, Smem<B> &sm,
     Ctrl *ctrl = p.ctrl;
     Pushers pu{{sm.queue[wid], 0}, {sm.queue_far[wid], 0}, Sink{nullptr, nullptr, 0u, ctrl, nullptr},
                Sink{nullptr, nullptr, 0u, ctrl, nullptr}, kInf};
-    LoopResult r{0u, 0ull, 0ull, 0u, 0ull};
+    LoopResult r{0u, 0ull, 0ull, 0u, 0ull, 0u};
     const bool lead = tm.id == 0 && threadIdx.x == 0;
     const bool all = p.reduce_all != 0;
     const uint32_t n = static_cast<uint32_t>(p.n);
@@ -190,7 +190,7 @@ __device__ __forceinline__ LoopResult run_topology(const Params &p, Smem<B> &sm,
 
 // One topology-driven query per cooperative launch.
 template <int B, class Op>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(Op::kMinWaves))) void topology_kernel(
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(fit_waves<B, Op::kMinWaves>()))) void topology_kernel(
     Params p) {
     __shared__ Smem<B> sm;
     const Team tm = whole_grid();

@@ -80,11 +80,11 @@ class irgl_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_uint32),
                 ("items", ctypes.c_uint64), ("edges", ctypes.c_uint64),
                 ("max_frontier", ctypes.c_uint32), ("grid", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("block", ctypes.c_int32), ("heavy_pulls", ctypes.c_uint32),
                 ("frontier_edges", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 STATS_BYTES = ctypes.sizeof(irgl_stats)

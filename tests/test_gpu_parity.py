@@ -260,6 +260,58 @@ def test_sssp_light_heavy_split(irgl):
         irgl.irgl_graph_set_delta(hr, 0)
 
 
+def _star_with_hub(leaves):
+    """Source 0 joined to `leaves` leaves by weight-1 edges, and a hub (the
+    last vertex) joined to every leaf by weight-100 edges; symmetric."""
+    h = leaves + 1
+    a = [0] * leaves + [h] * leaves
+    b = list(range(1, leaves + 1)) * 2
+    w = [1] * leaves + [100] * leaves
+    g = gg.from_edges(leaves + 2, a + b, b + a, w + w, name=f"star{leaves}_hub")
+    g.symmetric = True
+    return g
+
+
+def test_sssp_pull_heavy_pass(irgl):
+    """On a split symmetric graph, a bucket whose listed vertices carry many
+    heavy edges relaxes them as a pull: each vertex beyond the bucket reads its
+    own heavy range for the bucket's vertices (stats heavy_pulls counts these
+    passes).  A vertex beyond the bucket whose heavy range is longer than one
+    thread's pull limit (1024 edges) sends that pass back to the push form.
+    Distances equal the oracle's either way, with parents, at every block
+    size; on an R-MAT graph over several steps and sources pulls do happen."""
+    pulls = {}
+    for leaves in (1000, 2000):
+        g = _dev(_star_with_hub(leaves))
+        hr = irgl.upload(g, reorder=True)
+        irgl.irgl_graph_set_delta(hr, 10)
+        for cfg in (None, {"block": 256}, {"block": 1024}):
+            _, st = _check_query(irgl, g, hr, SSSP, 0, cfg, with_parent=True)
+            pulls.setdefault(leaves, set()).add(st["heavy_pulls"])
+    # the hub's 1000 heavy edges are pulled; its 2000 are pushed (one pass fewer)
+    assert len(pulls[1000]) == 1 and len(pulls[2000]) == 1
+    assert min(pulls[1000]) >= 1 and min(pulls[1000]) == min(pulls[2000]) + 1
+    g = _dev(gg.rmat(14, seed=91, weight_seed=92, wmax=255))
+    assert g.symmetric
+    hr = irgl.upload(g, reorder=True)
+    srcs = gg.pick_sources(g, 3, seed=93)
+    total = 0
+    for delta in (16, 64, 128):
+        irgl.irgl_graph_set_delta(hr, delta)
+        for src in srcs:
+            _, st = _check_query(irgl, g, hr, SSSP, src, None, with_parent=False)
+            total += st["heavy_pulls"]
+        _, st = _check_query(irgl, g, hr, SSSP, srcs[0], {"block": 1024}, with_parent=True)
+        total += st["heavy_pulls"]
+    assert total > 0
+    # not symmetric: the same graph declared directed never pulls
+    g.symmetric = False
+    hd = irgl.upload(g, reorder=True)
+    irgl.irgl_graph_set_delta(hd, 64)
+    _, st = _check_query(irgl, g, hd, SSSP, srcs[0], None, with_parent=False)
+    assert st["heavy_pulls"] == 0
+
+
 @pytest.mark.parametrize("reduce", [0, 1])
 def test_topology_driven_iterate(irgl, reduce):
     """IRGL_MODE_TOPOLOGY (a ForAll over every node whose invocation returns
