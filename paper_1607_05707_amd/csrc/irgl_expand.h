@@ -277,15 +277,24 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
     if (t_grid > B && cnt_in < stride) t_grid = B;
     // Tiles of B items: first one per workgroup, then (with tile_ctr) taken
     // from a shared counter, so that workgroups with light tiles take more.
+    // SSSP: such a worklist would fill only cnt_in / B workgroups, and one
+    // tile of B medium-degree vertices (a light phase just after the first
+    // hubs) then keeps one workgroup busy for a tenth of the query; its tiles
+    // hold ceil(cnt_in / team size) items instead (at least 128), so that
+    // every workgroup takes a share.  Consecutive items stay on consecutive
+    // threads (pushes of one wavefront are often neighbouring vertices).
+    const uint32_t tsz = (Op::kFar && cnt_in < stride)
+                             ? min(static_cast<uint32_t>(B), max(128u, (cnt_in + tm.size - 1) / tm.size))
+                             : static_cast<uint32_t>(B);
     uint32_t tile = tm.id;
     for (;;) {
-        const uint32_t base = tile * B;
+        const uint32_t base = tile * tsz;
         if (base >= cnt_in) break;  // uniform across the workgroup
         const uint32_t i = base + tid;
         int v = -1, r0 = 0, r1 = 0;
         uint32_t val = 0;
         bool hp = false, ex = false;
-        if (i < cnt_in) {
+        if (static_cast<uint32_t>(tid) < tsz && i < cnt_in) {
             v = in ? in[i] : static_cast<int>(i);
             if (static_cast<uint32_t>(v) >= n) {  // never expected: a corrupt worklist entry
                 set_error(pu.sk.ctrl, kErrInternal, false);
