@@ -352,6 +352,8 @@ __device__ __forceinline__ void pull_level(const Params &p, uint32_t next, Team 
 // it raises *big, and the caller runs the push pass after all.
 constexpr int kPullMaxRange = 1024;
 
+constexpr int kPullBatch = 8;
+
 template <int B, class Op>
 __device__ __forceinline__ void pull_heavy(const Params &p, const Op &hop, uint32_t lo, uint32_t bucket, Team tm,
                                            Pushers &pu, unsigned long long &scanned, uint32_t *big) {
@@ -380,17 +382,30 @@ __device__ __forceinline__ void pull_heavy(const Params &p, const Op &hop, uint3
                 r1 = r0;
             }
             unsigned long long best = du;
-            for (int x = r0; x < r1; ++x) {
-                const int v = p.col[x];
-                if (p.hstamp[v] != bucket) continue;
-                const unsigned long long c =
-                    static_cast<unsigned long long>(p.val[v]) + static_cast<unsigned long long>(p.w[x]);
-                if (c < best) {
-                    best = c;
-                    e[0] = x;
-                    sv[0] = v;
-                    dv[0] = p.val[v];
-                    act[0] = true;
+            // kPullBatch entries per step: their column loads, then their
+            // bucket-stamp probes, are in flight together (a long range is
+            // otherwise one dependent pair of loads per entry)
+            for (int x0 = r0; x0 < r1; x0 += kPullBatch) {
+                int vb[kPullBatch];
+                uint32_t hb[kPullBatch];
+#pragma unroll
+                for (int k = 0; k < kPullBatch; ++k) vb[k] = x0 + k < r1 ? p.col[x0 + k] : -1;
+#pragma unroll
+                for (int k = 0; k < kPullBatch; ++k) hb[k] = vb[k] >= 0 ? p.hstamp[vb[k]] : ~bucket;
+#pragma unroll
+                for (int k = 0; k < kPullBatch; ++k) {
+                    if (hb[k] != bucket) continue;
+                    const int v = vb[k];
+                    const uint32_t dvv = p.val[v];
+                    const unsigned long long c =
+                        static_cast<unsigned long long>(dvv) + static_cast<unsigned long long>(p.w[x0 + k]);
+                    if (c < best) {
+                        best = c;
+                        e[0] = x0 + k;
+                        sv[0] = v;
+                        dv[0] = dvv;
+                        act[0] = true;
+                    }
                 }
             }
             d[0] = static_cast<int>(u);
