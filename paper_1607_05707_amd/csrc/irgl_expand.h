@@ -212,6 +212,15 @@ __device__ __forceinline__ void stride_range(const Op &op, const int32_t *__rest
 // *hub_ctr) instead of being expanded here.  Every thread of every workgroup
 // must call it (it may synchronise the workgroup).
 // ---------------------------------------------------------------------------
+// Small worklists: a range of at least kSmallDefer entries goes to the grid
+// tier (one workgroup per chunk) rather than to its one wavefront, which
+// would walk it in ceil(deg / (64 U)) dependent rounds.  The first BFS
+// invocations on R-MAT (tens of items, tens of thousands of entries) then
+// end with the hub phase, not with one wavefront's long walk: RMAT-22 BFS
+// 368 against 386 us per query at B (1024), RMAT-21 304 against 314; SSSP
+// and the road grid unchanged; 128 and 512 within 1% of 256.
+constexpr int kSmallDefer = 256;
+
 template <int B, class Op>
 __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t cnt_in, uint32_t n,
                                        const int32_t *__restrict__ row_ptr,
@@ -231,7 +240,8 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
     // Small worklist (no more items than wavefronts in the team): one item per
     // wavefront, dealt across workgroups first, so that the ranges of a few
     // items are not walked one after another by a few workgroups.  Ranges of
-    // B or more edges go to the grid tier.
+    // kSmallDefer or more entries go to the grid tier (when its list is full,
+    // to the wavefront after all).
     if (t_grid > 0 && cnt_in <= tm.size * NW) {
         const uint32_t i = static_cast<uint32_t>(wid) * tm.size + tm.id;
         if (i >= cnt_in) return;  // uniform across the wavefront
@@ -253,7 +263,7 @@ __device__ __forceinline__ void expand(const int32_t *__restrict__ in, uint32_t 
         if (ex) pu.hminv = min(pu.hminv, val);  // every expansion, listed or not
         const int deg = r1 - r0;
         if (lane == 0) edges += static_cast<unsigned long long>(deg);
-        if (deg >= B) {  // a range of a whole round or more goes to the grid tier
+        if (deg >= kSmallDefer) {  // a range of several wavefront rounds goes to the grid tier
             int listed = 0;
             if (lane == 0) {
                 const unsigned long long old = atomicAdd(
