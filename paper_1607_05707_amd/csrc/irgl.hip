@@ -146,6 +146,16 @@ constexpr uint32_t kTailDiv = 16;
 // listed, runs its heavy pass as a pull.
 constexpr uint32_t kPullHeavyDiv = 2;
 constexpr uint32_t kPullOpenDiv = 2;
+// Once 7/8 of the partition's heavy entries have been listed, thresholds
+// rise by kStepGrow steps at a time: on R-MAT the first one or two buckets
+// settle nearly every vertex, and each of the small buckets after them costs
+// three or four invocations.  Chosen on the held-out scales 21 and 23 (32
+// sources, ms per query; one step / 2 / 4 / 8 / 16 steps): RMAT-21 1.84 /
+// 1.65 / 1.55 / 1.48 / 1.48, RMAT-23 4.17 / 3.81 / 3.66 / 3.58 / 3.59;
+// benchmark scale 22: 2.65 / 2.40 / 2.29 / 2.21 / 2.22; scale 20 1.37 /
+// 1.32 / 1.29 / 1.29 / 1.28.  Triggering at 3/4 instead of 7/8 made no
+// difference; road grids and the 64x64 grid are unchanged.
+constexpr uint32_t kStepGrow = 8;
 // Step of the light/heavy partition on a scale-free graph, as a fraction of
 // the mean weight W: each heavy edge is then relaxed once, while a smaller
 // step adds buckets (one barrier each).  Measured on R-MAT graphs of scales
@@ -550,6 +560,7 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
             p.pull_heavy_div = kPullHeavyDiv;
             p.pull_open_div = kPullOpenDiv;
             p.heavy_m = g->heavy_m;
+            p.step_grow = kStepGrow;
         }
     }
     p.val = g->perm ? reinterpret_cast<uint32_t *>(base + L.rval) : out;

@@ -112,6 +112,7 @@ __device__ __forceinline__ Params task_params(const BatchParams &bp, const TaskD
     p.shadow16 = 0;
     p.pull_heavy_div = 0;
     p.pull_open_div = 0;
+    p.step_grow = 0;
     p.heavy_m = 0;
     return p;
 }

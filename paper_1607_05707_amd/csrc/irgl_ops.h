@@ -110,6 +110,9 @@ struct Params {
     // 0 = no such bound.  heavy_m = heavy edges of the partition.
     uint32_t pull_open_div;
     unsigned long long heavy_m;
+    // SSSP with the pull bookkeeping: once 7/8 of the heavy entries have been
+    // listed, thresholds rise by step_grow steps at a time; 0 = one step
+    uint32_t step_grow;
 };
 
 // ---------------------------------------------------------------------------

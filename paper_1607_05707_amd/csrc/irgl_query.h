@@ -508,9 +508,21 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             // transfer invocation (SSSP only): far list tr -> next worklist / far list tr + 1.
             // With an empty far list (only a heavy pass left) the threshold
             // rises by one step, so the heavy results keep their bucket order.
+            // heavy entries listed by the drained bucket, and by all before it
+            const unsigned long long hs =
+                p.pull_heavy_div ? __hip_atomic_load(&ctrl->hsum[tr % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0ull;
+            const unsigned long long open = p.heavy_m > hdone ? p.heavy_m - hdone : 0ull;
+            hdone += hs;
+            // once nearly every heavy entry has been listed, the buckets left
+            // hold few vertices: wider ones cost fewer invocations
+            const uint32_t step = (p.step_grow && p.heavy_m && hdone * 8 >= p.heavy_m * 7 &&
+                                   p.delta <= kInf / p.step_grow)
+                                      ? p.delta * p.step_grow
+                                      : p.delta;
             uint32_t t_new =
-                far_n ? next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), p.delta)
-                      : raise_threshold(thresh, p.delta);
+                far_n ? next_threshold(thresh, load_agent(&ctrl->far_min[tr % 3]), step)
+                      : raise_threshold(thresh, step);
             // the last buckets of a scale-free graph hold few vertices each,
             // and each costs invocations (barriers): once the far list is
             // small next to the work done, finish without a threshold
@@ -540,11 +552,6 @@ __device__ __forceinline__ LoopResult run_iterate(const Params &p, Smem<B> &sm, 
             // then the vertices it scans are those beyond the threshold.
             const uint32_t hm = load_agent(&ctrl->hmin[tr % 3]);
             const uint32_t lo = hm >= kInf - p.delta ? kInf : hm + p.delta;
-            const unsigned long long hs =
-                p.pull_heavy_div ? __hip_atomic_load(&ctrl->hsum[tr % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                 : 0ull;
-            const unsigned long long open = p.heavy_m > hdone ? p.heavy_m - hdone : 0ull;
-            hdone += hs;
             bool pull_h = nheavy > 0 && p.pull_heavy_div && lo >= thresh &&
                           hs * p.pull_heavy_div >= static_cast<unsigned long long>(p.n) &&
                           (p.pull_open_div == 0 || hs * p.pull_open_div >= open);
