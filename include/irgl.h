@@ -174,7 +174,8 @@ typedef struct irgl_config {
                              and X > 16 D (scale-free): W from 2^26 edges on;
                              on a relabelled weighted upload, whose SSSP copy
                              is partitioned into light and heavy edges at the
-                             step, W / 4 from 2^25 edges and W / 2 from 2^24;
+                             step, W / 8 from 2^22 edges if IRGL_SYMMETRIC,
+                             else W / 4 from 2^25 edges and W / 2 from 2^24;
                              otherwise (and without IRGL_VALIDATE)
                              IRGL_DELTA_NONE (plain Bellman-Ford order).  A
                              vertex whose distance has not changed since its

@@ -164,9 +164,21 @@ constexpr uint32_t kStepGrow = 8;
 // without a step, scale 22: 3.53 against 5.02, scale 23: 5.93 against 8.95;
 // each within 2% of the best step tried), from 2^24 edges W/2 (scale 20:
 // 1.83 against 2.06), below that no step (scale 18: 1.10 against 1.45).
+// Those steps predate the growth of the step after the heavy passes, which
+// runs on symmetric graphs; there, re-derived with the growth (16 sources,
+// ms per query at steps 8 / 12 / 16 / 20 / 24 / 31 / 63, W = 128): held-out
+// scale 21 1.80 / 1.50 / 1.42 / 1.49 / 1.42 / 1.49 / 1.82, held-out scale 23
+// 4.09 / 3.60 / 3.48 / 3.44 / 3.48 / 3.56 / 4.55; benchmark scale 22 2.67 /
+// 2.20 / 2.11 / 2.16 / 2.13 / 2.21 / 2.63; scale 20 1.41 / 1.26 / 1.10 /
+// 1.09 / 1.17 / 1.12 / 1.28 (no step: 1.30 at W/2's rule); scale 18 (7.9M
+// edges) 0.99 / 0.88 / 0.81 / 0.82 / 0.82 / 0.79 / 0.83 (no step: 0.84).
+// A symmetric scale-free graph takes W/8 from 2^22 edges: the best step or
+// within 2.4% of it at every scale.
 constexpr double kSplitDeltaScale = 0.25;
 constexpr int64_t kSplitQuarterMinEdges = int64_t(1) << 25;
 constexpr int64_t kSplitHalfMinEdges = int64_t(1) << 24;
+constexpr double kSplitGrowScale = 0.125;
+constexpr int64_t kSplitGrowMinEdges = int64_t(1) << 22;
 constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Per-device facts, looked up once.
@@ -890,7 +902,8 @@ uint32_t delta_rule(const irgl_graph_s *g, bool partitioned) {
     } else if (static_cast<double>(g->max_degree) <= kSkew * mean_deg) {
         d = kDeltaDenseScale * mean_w / mean_deg;
     } else if (partitioned) {
-        if (g->m >= kSplitQuarterMinEdges) d = kSplitDeltaScale * mean_w;
+        if ((g->flags & IRGL_SYMMETRIC) && g->m >= kSplitGrowMinEdges) d = kSplitGrowScale * mean_w;
+        else if (g->m >= kSplitQuarterMinEdges) d = kSplitDeltaScale * mean_w;
         else if (g->m >= kSplitHalfMinEdges) d = 2.0 * kSplitDeltaScale * mean_w;
         else return IRGL_DELTA_NONE;
     } else {

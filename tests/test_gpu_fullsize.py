@@ -100,11 +100,11 @@ def test_rmat22_sssp_full_size(irgl, rmat22):
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
     ws = irgl.workspace(hg, SSSP, False, BENCH_CFG)
     stats = irgl.stats_tensor(dev)
-    # scale-free with more than 2^25 edges, relabelled weighted upload (rows
-    # split into light and heavy edges): the near/far step is a quarter of
-    # the mean weight
+    # symmetric scale-free with more than 2^22 edges, relabelled weighted
+    # upload (rows split into light and heavy edges): the near/far step is an
+    # eighth of the mean weight
     mean_w = float(np.asarray(w, dtype=np.uint32).astype(np.uint64).sum()) / g.m
-    assert irgl.irgl_graph_default_delta(hg) == int(0.25 * mean_w)
+    assert irgl.irgl_graph_default_delta(hg) == int(mean_w / 8.0)
     compare = (0, 31, 63)
     for i in range(64):
         src = g.sources[i]

@@ -454,6 +454,12 @@ def test_watchdog_and_abort_forced_from_host(irgl):
     _check_query(irgl, g, hg, BFS, 0, {"abort_flag": flag.data_ptr()})
 
 
+def _directed(g):
+    """The same arrays uploaded without the symmetric promise."""
+    g.symmetric = False
+    return g
+
+
 def _expected_default_delta(g, validated=True, partitioned=False):
     """The default near/far step written out from the graph's shape: mean
     weight W, mean out-degree D, largest out-degree X (host arrays);
@@ -468,6 +474,8 @@ def _expected_default_delta(g, validated=True, partitioned=False):
         d = 32.0 * mean_w / max(1.0, mean_deg)
     elif x <= 16.0 * mean_deg:
         d = 16.0 * mean_w / mean_deg
+    elif partitioned and g.symmetric and g.m >= 1 << 22:
+        d = mean_w / 8.0
     elif partitioned and g.m >= 1 << 25:
         d = mean_w / 4.0
     elif partitioned and g.m >= 1 << 24:
@@ -484,7 +492,8 @@ def test_default_near_far_step(irgl):
         (gg.uniform_random(1 << 14, 16.0, seed=61, weight_seed=62, wmax=1000), "near-regular, D 16"),
         (gg.uniform_random(1 << 14, 32.0, seed=63, weight_seed=64, wmax=1000), "near-regular, D 32"),
         (gg.rmat(14, seed=65, weight_seed=66, wmax=255), "scale-free, below 2^24 edges"),
-        (gg.rmat(20, seed=70, weight_seed=71, wmax=255), "scale-free, 2^24 to 2^25 edges"),
+        (gg.rmat(20, seed=70, weight_seed=71, wmax=255), "scale-free, symmetric, 2^24 to 2^25 edges"),
+        (_directed(gg.rmat(20, seed=70, weight_seed=71, wmax=255)), "scale-free, declared directed, 2^24 to 2^25"),
         (gg.config_road(width=64), "road-like, D < 8"),
         (gg.rmat(12, seed=67), "unweighted"),
     ]
