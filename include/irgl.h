@@ -163,7 +163,7 @@ typedef struct irgl_config {
                              the frontier's edges exceed the unexplored edges /
                              do_alpha; default 14; IRGL_DO_OFF = always top-down */
     uint32_t do_beta;     /* ... and back to top-down when the frontier holds fewer
-                             than n / do_beta vertices (default 24) */
+                             than n / do_beta vertices (default 96) */
     uint32_t delta;       /* SSSP: near/far threshold step.  Distances below the
                              threshold are expanded in bulk-synchronous invocations;
                              larger ones wait on a far list until the threshold has

@@ -284,7 +284,11 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
     // direction optimization needs in-edges = out-edges and the outlined loop
     const bool sym = (g->flags & IRGL_SYMMETRIC) != 0;
     r.do_alpha = (c && c->do_alpha) ? c->do_alpha : 14u;
-    r.do_beta = (c && c->do_beta) ? c->do_beta : 24u;
+    // back to top-down below n / 96 frontier vertices (16 sources, us per
+    // query at 24 / 48 / 96 / 192: RMAT-20 234 / 230 / 229 / 229, RMAT-21
+    // 310 / 308 / 308 / 305, RMAT-22 366 / 363 / 360 / 360, RMAT-23 565 /
+    // 557 / 558 / 558, road 4096^2 unchanged)
+    r.do_beta = (c && c->do_beta) ? c->do_beta : 96u;
     if (!sym || r.do_alpha == IRGL_DO_OFF || r.mode != IRGL_MODE_PERSISTENT) r.do_alpha = 0;
     r.trace_len = (c && c->trace) ? c->trace_len : 0u;
     r.trace = (c && c->trace) ? reinterpret_cast<unsigned long long *>(c->trace) : nullptr;

@@ -4,7 +4,7 @@
 //
 //   irgl_run FILE [--kinds bfs,sssp] [--sources K] [--reps R] [--warmup W]
 //                 [--block B] [--mode 0|1] [--t-grid T] [--t-bitmap T]
-//                 [--do-alpha A] [--delta D] [--calibrate MB] [--reorder 0|1]
+//                 [--do-alpha A] [--do-beta B] [--delta D] [--calibrate MB] [--reorder 0|1]
 //                 [--set-delta D] [--maps FILE]
 //
 // --calibrate MB first copies MB megabytes device-to-device once (a plain
@@ -169,6 +169,7 @@ int main(int argc, char **argv) {
         else if (k == "--t-grid") cfg.t_grid = std::atoi(v);
         else if (k == "--t-bitmap") cfg.t_bitmap = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--do-alpha") cfg.do_alpha = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
+        else if (k == "--do-beta") cfg.do_beta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--delta") cfg.delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
         else if (k == "--reorder") reorder = std::atoi(v);
         else if (k == "--set-delta") set_delta = static_cast<uint32_t>(std::strtoul(v, nullptr, 0));
