@@ -87,9 +87,14 @@ __device__ __forceinline__ SsspOp make_op<SsspOp>(const Params &p, uint32_t it, 
                                                   bool heavy) {
     SsspOp op{p.val, p.w, p.stamp, p.far_flag, thresh, it, p.ctrl, p.visited, p.shadow};
     op.shadow16 = p.shadow16;
-    op.split = p.split;
+    // without a threshold (the bucketing has ended) an expansion relaxes the
+    // whole row and lists nothing: every vertex listed before has its heavy
+    // pass in the transfer that ended the bucketing, so no heavy pass (and
+    // no transfer invocation) is left
+    const bool whole = !heavy && thresh == kInf;
+    op.split = whole ? nullptr : p.split;
     op.expd = heavy ? nullptr : p.expd;
-    op.hstamp = (heavy || !p.split) ? nullptr : p.hstamp;
+    op.hstamp = (heavy || whole || !p.split) ? nullptr : p.hstamp;
     op.bucket = bucket;
     op.heavy = heavy ? 1u : 0u;
     return op;
