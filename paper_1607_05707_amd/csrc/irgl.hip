@@ -139,8 +139,17 @@ uint32_t delta_rule(const irgl_graph_s *g, bool partitioned);
 // The scale-free branch of the rule (mean degree at least kDeltaMinDegree,
 // largest out-degree above kSkew times the mean), from the validation pass.
 bool scale_free(const irgl_graph_s *g);
-// Far-list divisor of the bucketing's early end on split scale-free graphs.
-constexpr uint32_t kTailDiv = 16;
+// Far-list divisor of the bucketing's early end on split scale-free graphs:
+// it ends once the far list holds fewer than (items popped so far) /
+// kTailDiv vertices.  Re-derived once an expansion without a threshold
+// relaxes whole rows (no heavy pass left), with the step W/8 and the
+// threshold growth (32 sources, ms per query at divisors 16 / 4 / 2 / 1,
+// and at 1 with the far list compared against 2 / 4 / 16 times the items):
+// held-out RMAT-21 1.40 / 1.36 / 1.30 / 1.19, then 1.49 / 1.87 / 2.20;
+// held-out RMAT-23 3.42 / 3.27 / 3.06 / 3.10-3.15, then 3.58 / 5.18 / 5.49;
+// benchmark RMAT-22 2.03 / 1.97 / 1.84 / 1.72, then 2.25 / 2.86 / 3.13;
+// RMAT-20 1.09 / 1.04 / 1.01 / 0.94.
+constexpr uint32_t kTailDiv = 1;
 // A bucket whose listed vertices hold at least n / kPullHeavyDiv heavy edges,
 // and at least 1 / kPullOpenDiv of the heavy edges of the vertices not yet
 // listed, runs its heavy pass as a pull.
@@ -562,8 +571,9 @@ irgl_status run(int kind, irgl_graph g, int32_t src, uint32_t *out, int32_t *par
         p.hlist = reinterpret_cast<int32_t *>(base + L.hlist);
         p.hstamp = reinterpret_cast<uint32_t *>(base + L.hstamp);
         p.hcap = static_cast<uint32_t>(g->n);
-        // RMAT-22, 32 sources: 3.65 ms per query against 3.74 ms without
-        // (30 instead of 37 invocations; a divisor of 64: 3.67 ms)
+        // the early end of the bucketing (first measured at divisor 16: RMAT-22
+        // 3.65 ms per query against 3.74 without, 30 instead of 37
+        // invocations; the divisor now is the one derived with kTailDiv) and
         // the 16-bit shadow (distances of scale-free graphs are small): RMAT-22
         // 3.47 against 3.54 ms, RMAT-23 5.82 against 5.95 ms (32 sources)
         if (scale_free(g)) {
