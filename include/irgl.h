@@ -135,7 +135,8 @@ typedef struct irgl_config {
     int32_t t_block;      /* workgroup tier threshold, >= t_wave (default: t_grid) */
     int32_t t_grid;       /* grid tier threshold, >= t_block: such vertices are split
                              into equal chunks over all workgroups after a grid
-                             barrier (default max(512, t_block); lowered to
+                             barrier (default max(512, t_block), max(256,
+                             t_block) for outlined SSSP; lowered to
                              block for a worklist with fewer items than the grid has
                              threads); IRGL_GRID_TIER_OFF = never */
     int32_t grid;         /* workgroups; 0 = co-resident limit (occupancy x CUs) */

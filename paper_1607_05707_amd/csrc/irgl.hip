@@ -263,6 +263,11 @@ int default_block(int kind) { return kind == IRGL_KIND_BFS ? 1024 : 512; }
 // 1024-thread workgroups 13.0 ms at 512, 17.2 ms at 256, 20.4 ms at 2048;
 // BFS within 2% from 512 to 4096).
 constexpr int kGridTier = 512;
+// Outlined SSSP queries take hubs from 256 edges (16 sources, ms per query
+// at 512 / 256: held-out RMAT-21 1.12 / 1.09, RMAT-23 3.32 / 3.31,
+// benchmark RMAT-22 1.73 / 1.70, RMAT-20 0.90 / 0.91, road 4096^2 7.82 /
+// 7.83; topology-driven queries lose at 256, see above).
+constexpr int kGridTierSssp = 256;
 
 irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *out) {
     Cfg r;
@@ -273,7 +278,9 @@ irgl_status resolve(const irgl_graph_s *g, int kind, const irgl_config *c, Cfg *
         return IRGL_ERR_CONFIG;
     // the grid tier takes hubs from a fixed kGridTier edges on
     int t_grid = c ? c->t_grid : 0;
-    if (t_grid == 0) t_grid = std::max(kGridTier, c ? c->t_block : 0);
+    if (t_grid == 0)
+        t_grid = std::max(kind == IRGL_KIND_SSSP && r.mode == IRGL_MODE_PERSISTENT ? kGridTierSssp : kGridTier,
+                          c ? c->t_block : 0);
     resolve_tiers(r.block, c ? c->t_wave : 0, c ? c->t_block : 0, t_grid, &r.t_wave, &r.t_block, &r.t_grid);
     if (r.t_wave < 1 || r.t_block < r.t_wave || r.t_grid < 0 || (r.t_grid > 0 && r.t_grid < r.t_block))
         return IRGL_ERR_CONFIG;
