@@ -163,8 +163,13 @@ constexpr uint32_t kPullOpenDiv = 2;
 // 1.65 / 1.55 / 1.48 / 1.48, RMAT-23 4.17 / 3.81 / 3.66 / 3.58 / 3.59;
 // benchmark scale 22: 2.65 / 2.40 / 2.29 / 2.21 / 2.22; scale 20 1.37 /
 // 1.32 / 1.29 / 1.29 / 1.28.  Triggering at 3/4 instead of 7/8 made no
-// difference; road grids and the 64x64 grid are unchanged.
-constexpr uint32_t kStepGrow = 8;
+// difference; road grids and the 64x64 grid are unchanged.  Since the
+// bucketing ends once the far list holds fewer vertices than have been
+// popped (kTailDiv 1), the small buckets it saved are gone, and growth by
+// 0 (off) / 4 / 8 / 16 measures RMAT-21 1.14 / 1.15 / 1.16 / 1.15, RMAT-22
+// 1.67 / 1.67 / 1.68 / 1.69, RMAT-23 3.14 / 3.18 / 3.14 / 3.18, RMAT-20
+// 0.94 / 0.95 / 0.94 / 0.93 ms: it is off.
+constexpr uint32_t kStepGrow = 0;
 // Step of the light/heavy partition on a scale-free graph, as a fraction of
 // the mean weight W: each heavy edge is then relaxed once, while a smaller
 // step adds buckets (one barrier each).  Measured on R-MAT graphs of scales
